@@ -1,0 +1,182 @@
+/*
+ * pgo.h -- C ABI of the MI355X (gfx950) PRADMM sweep library.
+ *
+ * Problem (Model section, eq. 1): n poses (p_i unit quaternion, t_i in R^3)
+ * and m directed edges e = (i -> j) carrying a relative rotation R~_ij, a
+ * relative translation t~_ij and isotropic precisions kappa_ij (rotation)
+ * and tau_ij (translation).  The library runs the Parallelizable Riemannian
+ * ADMM of Alg. 1 on the split model (eq. 2): each sweep updates, for every
+ * vertex in parallel, p (projection onto the unit sphere, App. B.1), q
+ * (App. B.2), t (App. B.3), s (App. B.4), then the multipliers lambda and z
+ * with relaxation step gamma in (0, 2) (eq. 3e-3f).
+ *
+ * Conventions
+ *   - quaternions are [w, x, y, z] with the Hamilton product of App. A.2;
+ *     rotation matrices are row-major 3x3, R v = Im(q [0, v] q^*).
+ *   - Sigma1 = tau_e I, Sigma2 = kappa_e I per edge; one penalty
+ *     beta = beta1 = beta2; proximal weights H_s = h_s I.
+ *   - state of a vertex, as 21 doubles: p(4) q(4) t(3) s(3) lambda(4) z(3).
+ *
+ * Ownership: host arrays passed to pgo_create* are read during the call and
+ * copied; the caller keeps them.  A handle owns all of its device memory
+ * until pgo_destroy.  Output buffers are caller-allocated.  Pointers named
+ * *_dev are device pointers on the handle's device.
+ *
+ * Threading: a handle is not thread-safe.  All work of a handle is enqueued
+ * on one HIP stream (its own, or the one given to pgo_set_stream); calls
+ * that return host data synchronise that stream.
+ *
+ * Errors: every call returns a pgo_status; pgo_last_error() returns a
+ * thread-local message describing the last failure.
+ */
+#ifndef PGO_H
+#define PGO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pgo_graph pgo_graph;
+
+typedef enum {
+  PGO_OK = 0,
+  PGO_EINVAL = 1,   /* invalid argument (message names the offending item) */
+  PGO_ENOMEM = 2,   /* device or host allocation failed */
+  PGO_EDEVICE = 3,  /* HIP runtime error (message carries hipGetErrorString) */
+  PGO_ENUMERIC = 4, /* a reduction found a non-finite value in the state */
+  PGO_ESTATE = 5    /* call not valid for this handle (e.g. wrong precision) */
+} pgo_status;
+
+typedef enum {
+  PGO_FP64 = 0, /* state, edges and arithmetic in double */
+  PGO_FP32 = 1  /* state, edges and accumulation in float; double for the
+                   boundary preparation, the cost/residual reductions and a
+                   p-update whose sum cancels (|v| < 1e-3 of the summed
+                   magnitudes) */
+} pgo_precision;
+
+typedef enum {
+  PGO_SCHED_AUTO = 0,  /* pick by graph sizes (or the autotuner's choice) */
+  PGO_SCHED_PHASE = 1, /* one kernel launch per phase; any graph size */
+  PGO_SCHED_GRAPH = 2  /* one persistent workgroup per graph runs all the
+                          sweeps of one pgo_iterate call (graphs of at most
+                          PGO_GRAPH_SCHED_MAX_N vertices) */
+} pgo_schedule;
+
+#define PGO_GRAPH_SCHED_MAX_N 65536
+
+typedef struct {
+  double h1, h2, h3, h4; /* proximal weights H_1..H_4 (defaults 1, 1e-3, 1e-3,
+                            1e-3: the experiment settings) */
+  int32_t precision;     /* pgo_precision, default PGO_FP64 */
+  int32_t schedule;      /* pgo_schedule, default PGO_SCHED_AUTO */
+  int32_t block;         /* threads per workgroup; 0 = library default */
+  int32_t device;        /* HIP device ordinal, default 0 */
+} pgo_options;
+
+/* Fill *opt with the defaults above. */
+void pgo_default_options(pgo_options* opt);
+
+/*
+ * pgo_create -- build a handle for one pose graph (Alg. 1 input: the graph,
+ * the measurements, the initial points).
+ *   n         number of poses, >= 1
+ *   R0, t0    initial rotations (n x 9, row-major) and translations (n x 3)
+ *   m         number of edges, >= 0 (< 2^31)
+ *   ei, ej    edge tails and heads (m each), 0 <= ei, ej < n, ei != ej
+ *   Rm, tm    measured relative rotations (m x 9) and translations (m x 3)
+ *   kappa,tau precisions (m each), finite and > 0
+ *   opt       options, or NULL for the defaults
+ * Every rotation must have det > 0 and ||R^T R - I||_F <= 1e-2; it is
+ * projected onto SO(3) on the device (FP64 3x3 Jacobi SVD polar factor) and
+ * converted to a unit quaternion.  A vertex quaternion's sign is chosen so
+ * that its first component of magnitude > 1e-6 is positive; each edge
+ * quaternion's sign so that <p_i^0 q~_e, p_j^0> >= 0 (the cost of model (1)
+ * depends on that sign and a rotation matrix does not fix it).  Initial
+ * state: q = p, s = t, lambda = z = 0.  Duplicate and reverse edges,
+ * isolated vertices and disconnected graphs are allowed.
+ * Returns PGO_EINVAL (bad input, message names it), PGO_ENOMEM, PGO_EDEVICE.
+ */
+pgo_status pgo_create(pgo_graph** out, int32_t n, const double* R0, const double* t0,
+                      int64_t m, const int32_t* ei, const int32_t* ej, const double* Rm,
+                      const double* tm, const double* kappa, const double* tau,
+                      const pgo_options* opt);
+
+/*
+ * pgo_create_batched -- G independent pose graphs in one handle.  Graph g
+ * owns poses voff[g]..voff[g+1]-1 and edges eoff[g]..eoff[g+1]-1 of the
+ * concatenated arrays (same layouts as pgo_create); ei/ej are graph-local
+ * (0 <= ei < voff[g+1]-voff[g]).  voff[0] = eoff[0] = 0, every graph has at
+ * least one pose, offsets are nondecreasing.  Sweeps, beta and gamma are
+ * shared by all graphs; costs and residuals are reported per graph.
+ */
+pgo_status pgo_create_batched(pgo_graph** out, int32_t G, const int64_t* voff,
+                              const int64_t* eoff, const double* R0, const double* t0,
+                              const int32_t* ei, const int32_t* ej, const double* Rm,
+                              const double* tm, const double* kappa, const double* tau,
+                              const pgo_options* opt);
+
+/* Use the given hipStream_t (e.g. torch.cuda.current_stream().cuda_stream)
+ * for all later work of the handle; NULL returns to the handle's own stream. */
+pgo_status pgo_set_stream(pgo_graph* g, void* hip_stream);
+
+/*
+ * pgo_iterate -- enqueue k PRADMM sweeps (Alg. 1 steps 2-6) with penalty
+ * beta > 0 and relaxation gamma in (0, 2) (open interval).  k = 0 is a
+ * no-op.  Asynchronous: returns once the work is enqueued.
+ */
+pgo_status pgo_iterate(pgo_graph* g, int32_t k, double beta, double gamma);
+
+/* Cost of model (1) at (p, t), one double per graph, accumulated in FP64. */
+pgo_status pgo_cost(pgo_graph* g, double* F);
+
+/*
+ * Residuals, 6 doubles per graph:
+ *   [0] ||p - q||, [1] ||t - s||,
+ *   [2] e = (||dlambda||^2 + ||dz||^2)/beta + beta(||dq||^2 + ||dt||^2)
+ *       (iteration residual of App. E.1; d = change over the last sweep,
+ *        beta of the last pgo_iterate call; 0 before any sweep),
+ *   [3] beta ||dq||, [4] beta ||ds|| (dual residuals),
+ *   [5] cost of model (1).
+ * All sums in FP64.  PGO_ENUMERIC if any value is not finite.
+ */
+pgo_status pgo_residuals(pgo_graph* g, double* out);
+
+/* Current poses: R(p_i) (n x 9, row-major) and t_i (n x 3); either may be NULL. */
+pgo_status pgo_get_poses(pgo_graph* g, double* R, double* t);
+
+/* Raw state, n x 21 doubles (see conventions); set_state restarts the
+ * residual history (the next residuals report d = 0 until a sweep runs). */
+pgo_status pgo_get_state(pgo_graph* g, double* state);
+pgo_status pgo_set_state(pgo_graph* g, const double* state);
+
+/* The prepared (projected, converted, sign-aligned) edge quaternions in the
+ * caller's edge order (m x 4) and vertex quaternions p^0 (n x 4); either may
+ * be NULL. */
+pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat0);
+
+/* Sizes of the handle; any pointer may be NULL. */
+pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
+                    int32_t* schedule, int32_t* block);
+
+/*
+ * pgo_autotune -- time the candidate schedules and workgroup sizes on this
+ * handle's own graphs (sweeps sweeps each, beta, gamma), keep the fastest for
+ * later pgo_iterate calls, and restore the state it found.  Reports the
+ * chosen schedule and block size through pgo_info.
+ */
+pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps);
+
+/* Release the handle and its device memory.  NULL is ignored. */
+void pgo_destroy(pgo_graph* g);
+
+/* Message for the last error on the calling thread ("" if none). */
+const char* pgo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PGO_H */

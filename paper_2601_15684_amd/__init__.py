@@ -1,0 +1,291 @@
+"""PRADMM sweep for SE(3) pose-graph optimisation on MI355X (gfx950).
+
+Thin Python binding of the C ABI in include/pgo.h: every function here has
+the C function's name and only marshals arguments (numpy float64/int32
+arrays in, numpy arrays out).  All of the method runs in the HIP kernels of
+libpgo.so.  The library is loaded on first use; if it has not been built,
+that first use raises (build it with ``python -m paper_2601_15684_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
+    "pgo_set_stream", "pgo_iterate", "pgo_cost", "pgo_residuals", "pgo_get_poses",
+    "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
+    "pgo_destroy", "pgo_last_error", "PoseGraph",
+    "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "LIB_PATH",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpgo.so")
+FP64, FP32 = 0, 1
+SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH = 0, 1, 2
+STATUS = {0: "PGO_OK", 1: "PGO_EINVAL", 2: "PGO_ENOMEM", 3: "PGO_EDEVICE", 4: "PGO_ENUMERIC",
+          5: "PGO_ESTATE"}
+
+
+class PgoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+class PgoOptions(C.Structure):
+    _fields_ = [("h1", C.c_double), ("h2", C.c_double), ("h3", C.c_double), ("h4", C.c_double),
+                ("precision", C.c_int32), ("schedule", C.c_int32), ("block", C.c_int32),
+                ("device", C.c_int32)]
+
+
+_P = C.c_void_p
+_D = C.POINTER(C.c_double)
+_I32 = C.POINTER(C.c_int32)
+_I64 = C.POINTER(C.c_int64)
+_lib = None
+
+_SIGNATURES = {
+    "pgo_default_options": (None, [C.POINTER(PgoOptions)]),
+    "pgo_create": (C.c_int, [C.POINTER(_P), C.c_int32, _D, _D, C.c_int64, _I32, _I32, _D, _D, _D, _D,
+                             C.POINTER(PgoOptions)]),
+    "pgo_create_batched": (C.c_int, [C.POINTER(_P), C.c_int32, _I64, _I64, _D, _D, _I32, _I32, _D, _D,
+                                     _D, _D, C.POINTER(PgoOptions)]),
+    "pgo_set_stream": (C.c_int, [_P, _P]),
+    "pgo_iterate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
+    "pgo_cost": (C.c_int, [_P, _D]),
+    "pgo_residuals": (C.c_int, [_P, _D]),
+    "pgo_get_poses": (C.c_int, [_P, _D, _D]),
+    "pgo_get_state": (C.c_int, [_P, _D]),
+    "pgo_set_state": (C.c_int, [_P, _D]),
+    "pgo_get_prepared": (C.c_int, [_P, _D, _D]),
+    "pgo_info": (C.c_int, [_P, _I64, _I64, _I32, _I32, _I32, _I32]),
+    "pgo_autotune": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32]),
+    "pgo_destroy": (None, [_P]),
+    "pgo_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """The loaded libpgo.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2601_15684_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _chk(status):
+    if status != 0:
+        raise PgoError(status, pgo_last_error())
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def _ip(a):
+    return a.ctypes.data_as(_I32) if a is not None else None
+
+
+def pgo_last_error() -> str:
+    return lib().pgo_last_error().decode()
+
+
+def pgo_default_options(**kw) -> PgoOptions:
+    o = PgoOptions()
+    lib().pgo_default_options(C.byref(o))
+    for k, v in kw.items():
+        if k == "h":
+            o.h1, o.h2, o.h3, o.h4 = v
+        elif k == "precision" and isinstance(v, str):
+            o.precision = {"fp64": FP64, "fp32": FP32}[v]
+        elif k == "schedule" and isinstance(v, str):
+            o.schedule = {"auto": SCHED_AUTO, "phase": SCHED_PHASE, "graph": SCHED_GRAPH}[v]
+        else:
+            setattr(o, k, v)
+    return o
+
+
+def pgo_create(n, R0, t0, ei, ej, Rm, tm, kappa, tau, options=None):
+    m = int(np.asarray(ei).shape[0])
+    arrs = [_f64(R0), _f64(t0), _i32(ei), _i32(ej), _f64(Rm), _f64(tm), _f64(kappa), _f64(tau)]
+    h = _P()
+    _chk(lib().pgo_create(C.byref(h), int(n), _dp(arrs[0]), _dp(arrs[1]), m, _ip(arrs[2]),
+                          _ip(arrs[3]), _dp(arrs[4]), _dp(arrs[5]), _dp(arrs[6]), _dp(arrs[7]),
+                          C.byref(options) if options is not None else None))
+    return h
+
+
+def pgo_create_batched(voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, tau, options=None):
+    voff = np.ascontiguousarray(voff, dtype=np.int64)
+    eoff = np.ascontiguousarray(eoff, dtype=np.int64)
+    arrs = [_f64(R0), _f64(t0), _i32(ei), _i32(ej), _f64(Rm), _f64(tm), _f64(kappa), _f64(tau)]
+    h = _P()
+    _chk(lib().pgo_create_batched(C.byref(h), int(voff.shape[0] - 1), voff.ctypes.data_as(_I64),
+                                  eoff.ctypes.data_as(_I64), _dp(arrs[0]), _dp(arrs[1]),
+                                  _ip(arrs[2]), _ip(arrs[3]), _dp(arrs[4]), _dp(arrs[5]),
+                                  _dp(arrs[6]), _dp(arrs[7]),
+                                  C.byref(options) if options is not None else None))
+    return h
+
+
+def pgo_set_stream(h, stream):
+    _chk(lib().pgo_set_stream(h, C.c_void_p(int(stream)) if stream else None))
+
+
+def pgo_iterate(h, k, beta, gamma):
+    _chk(lib().pgo_iterate(h, int(k), float(beta), float(gamma)))
+
+
+def pgo_info(h):
+    n, m = C.c_int64(), C.c_int64()
+    G, prec, sched, block = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _chk(lib().pgo_info(h, C.byref(n), C.byref(m), C.byref(G), C.byref(prec), C.byref(sched),
+                        C.byref(block)))
+    return dict(n=n.value, m=m.value, G=G.value, precision=prec.value, schedule=sched.value,
+                block=block.value)
+
+
+def pgo_cost(h):
+    out = np.empty(pgo_info(h)["G"], np.float64)
+    _chk(lib().pgo_cost(h, _dp(out)))
+    return out
+
+
+def pgo_residuals(h):
+    out = np.empty((pgo_info(h)["G"], 6), np.float64)
+    _chk(lib().pgo_residuals(h, _dp(out)))
+    return out
+
+
+def pgo_get_poses(h):
+    n = pgo_info(h)["n"]
+    R = np.empty((n, 3, 3), np.float64)
+    t = np.empty((n, 3), np.float64)
+    _chk(lib().pgo_get_poses(h, _dp(R), _dp(t)))
+    return R, t
+
+
+def pgo_get_state(h):
+    n = pgo_info(h)["n"]
+    out = np.empty((n, 21), np.float64)
+    _chk(lib().pgo_get_state(h, _dp(out)))
+    return out
+
+
+def pgo_set_state(h, state):
+    info = pgo_info(h)
+    s = _f64(state, (info["n"], 21))
+    _chk(lib().pgo_set_state(h, _dp(s)))
+
+
+def pgo_get_prepared(h):
+    info = pgo_info(h)
+    qe = np.empty((info["m"], 4), np.float64)
+    p0 = np.empty((info["n"], 4), np.float64)
+    _chk(lib().pgo_get_prepared(h, _dp(qe), _dp(p0)))
+    return qe, p0
+
+
+def pgo_autotune(h, beta, gamma, sweeps=10):
+    _chk(lib().pgo_autotune(h, float(beta), float(gamma), int(sweeps)))
+    return pgo_info(h)
+
+
+def pgo_destroy(h):
+    if h:
+        lib().pgo_destroy(h)
+
+
+def split_state(state):
+    """(n,21) state -> dict p, q, t, s, lam, z."""
+    s = np.asarray(state)
+    return dict(p=s[:, 0:4], q=s[:, 4:8], t=s[:, 8:11], s=s[:, 11:14], lam=s[:, 14:18], z=s[:, 18:21])
+
+
+class PoseGraph:
+    """Owning wrapper of one handle (single graph or batch)."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    @classmethod
+    def from_graph(cls, g, **opt):
+        return cls(pgo_create(g.n, g.R0.reshape(-1, 9), g.t0, g.ei, g.ej, g.Rm.reshape(-1, 9), g.tm,
+                              g.kappa, g.tau, pgo_default_options(**opt)))
+
+    @classmethod
+    def from_batch(cls, batch, **opt):
+        voff, eoff = batch.offsets()
+        c = batch.concat()
+        return cls(pgo_create_batched(voff, eoff, c["R0"].reshape(-1, 9), c["t0"], c["ei"], c["ej"],
+                                      c["Rm"].reshape(-1, 9), c["tm"], c["kappa"], c["tau"],
+                                      pgo_default_options(**opt)))
+
+    def iterate(self, k, beta, gamma):
+        pgo_iterate(self.h, k, beta, gamma)
+
+    def cost(self):
+        return pgo_cost(self.h)
+
+    def residuals(self):
+        return pgo_residuals(self.h)
+
+    def poses(self):
+        return pgo_get_poses(self.h)
+
+    def state(self):
+        return pgo_get_state(self.h)
+
+    def set_state(self, s):
+        pgo_set_state(self.h, s)
+
+    def prepared(self):
+        return pgo_get_prepared(self.h)
+
+    def info(self):
+        return pgo_info(self.h)
+
+    def autotune(self, beta, gamma, sweeps=10):
+        return pgo_autotune(self.h, beta, gamma, sweeps)
+
+    def set_stream(self, stream):
+        pgo_set_stream(self.h, stream)
+
+    def close(self):
+        if self.h:
+            pgo_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,733 @@
+// Host side of the C ABI declared in include/pgo.h: argument checking,
+// device memory ownership, the boundary preparation sequence, schedule
+// selection, the autotuner and the host<->device transfers.  All arithmetic
+// of the method runs in the kernels of sweep.hip, prep.hip and reduce.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+#include "pgo.h"
+
+using namespace pgo;
+
+namespace {
+
+thread_local std::string g_err;
+
+pgo_status fail(pgo_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+pgo_status hip_fail(hipError_t e, const char* what) {
+  return fail(e == hipErrorOutOfMemory ? PGO_ENOMEM : PGO_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr)                                   \
+  do {                                                 \
+    hipError_t e_ = (expr);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #expr);  \
+  } while (0)
+
+constexpr int64_t kChunk = 8192;  // items per reduction chunk
+
+}  // namespace
+
+struct pgo_graph {
+  int device = 0;
+  hipStream_t own_stream = nullptr;
+  hipStream_t stream = nullptr;
+  pgo_options opt{};
+  int64_t n = 0, m = 0;
+  int32_t G = 0;
+  int32_t max_n = 0;
+  std::vector<void*> allocs;
+  std::vector<int64_t> voff_h, eoff_h;
+  int32_t* voff32 = nullptr;
+  int32_t* order = nullptr;
+  int32_t *o_ptr = nullptr, *o_nbr = nullptr, *o_perm = nullptr;
+  int32_t *i_ptr = nullptr, *i_nbr = nullptr, *i_perm = nullptr;
+  void *o_tt = nullptr, *o_w = nullptr, *i_tt = nullptr, *i_w = nullptr;
+  void *cQ = nullptr, *cT = nullptr, *cS = nullptr;
+  void *p = nullptr, *q = nullptr, *lam = nullptr, *t = nullptr, *s = nullptr, *z = nullptr;
+  void *q_prev = nullptr, *lam_prev = nullptr, *t_prev = nullptr, *s_prev = nullptr,
+       *z_prev = nullptr;
+  int32_t *ei = nullptr, *ej = nullptr;
+  Q4<double>* qe = nullptr;
+  double *tm = nullptr, *kappa = nullptr, *tau = nullptr;
+  Q4<double>* p0 = nullptr;
+  int n_ech = 0, n_vch = 0;
+  int64_t *ec_beg = nullptr, *ec_end = nullptr, *vc_beg = nullptr, *vc_end = nullptr;
+  int32_t *g_ec_off = nullptr, *g_vc_off = nullptr;
+  double *part_e = nullptr, *part_v = nullptr, *red_out = nullptr;
+  double* iobuf = nullptr;  // n x 21 doubles, allocated on first use
+  int sched = PGO_SCHED_PHASE;
+  int block_phase = 256;
+  int block_graph = 256;
+  double last_beta = 1.0;
+  bool have_prev = false;
+  // captured launch sequence of the per-phase schedule
+  hipGraphExec_t gexec = nullptr;
+  int g_k = -1, g_block = -1;
+  double g_beta = 0, g_gamma = 0;
+};
+
+namespace {
+
+template <typename X>
+pgo_status dalloc(pgo_graph* g, X** ptr, size_t count) {
+  *ptr = nullptr;
+  if (count == 0) count = 1;
+  void* raw = nullptr;
+  hipError_t e = hipMalloc(&raw, count * sizeof(X));
+  if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+  g->allocs.push_back(raw);
+  *ptr = static_cast<X*>(raw);
+  return PGO_OK;
+}
+
+pgo_status dalloc_bytes(pgo_graph* g, void** ptr, size_t bytes) {
+  return dalloc<uint8_t>(g, reinterpret_cast<uint8_t**>(ptr), bytes);
+}
+
+void dfree(pgo_graph* g, void* ptr) {
+  if (!ptr) return;
+  auto it = std::find(g->allocs.begin(), g->allocs.end(), ptr);
+  if (it != g->allocs.end()) {
+    (void)hipFree(ptr);
+    g->allocs.erase(it);
+  }
+}
+
+template <typename X>
+pgo_status upload(pgo_graph* g, X** dst, const X* src, size_t count) {
+  pgo_status s = dalloc(g, dst, count);
+  if (s != PGO_OK) return s;
+  if (count) HIPCHK(hipMemcpyAsync(*dst, src, count * sizeof(X), hipMemcpyHostToDevice, g->stream));
+  return PGO_OK;
+}
+
+template <typename T>
+DevGraph<T> view(const pgo_graph* g) {
+  DevGraph<T> d;
+  d.n = int32_t(g->n);
+  d.o_ptr = g->o_ptr;
+  d.o_nbr = g->o_nbr;
+  d.o_tt = static_cast<const P4<T>*>(g->o_tt);
+  d.o_w = static_cast<const Q4<T>*>(g->o_w);
+  d.i_ptr = g->i_ptr;
+  d.i_nbr = g->i_nbr;
+  d.i_tt = static_cast<const P4<T>*>(g->i_tt);
+  d.i_w = static_cast<const Q4<T>*>(g->i_w);
+  d.cQ = static_cast<const T*>(g->cQ);
+  d.cT = static_cast<const T*>(g->cT);
+  d.cS = static_cast<const T*>(g->cS);
+  d.p = static_cast<Q4<T>*>(g->p);
+  d.q = static_cast<Q4<T>*>(g->q);
+  d.lam = static_cast<Q4<T>*>(g->lam);
+  d.t = static_cast<P4<T>*>(g->t);
+  d.s = static_cast<P4<T>*>(g->s);
+  d.z = static_cast<P4<T>*>(g->z);
+  d.q_prev = static_cast<Q4<T>*>(g->q_prev);
+  d.lam_prev = static_cast<Q4<T>*>(g->lam_prev);
+  d.t_prev = static_cast<P4<T>*>(g->t_prev);
+  d.s_prev = static_cast<P4<T>*>(g->s_prev);
+  d.z_prev = static_cast<P4<T>*>(g->z_prev);
+  return d;
+}
+
+bool finite_all(const double* a, size_t k) {
+  for (size_t i = 0; i < k; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+pgo_status check_options(const pgo_options& o) {
+  const double h[4] = {o.h1, o.h2, o.h3, o.h4};
+  for (int k = 0; k < 4; ++k)
+    if (!(std::isfinite(h[k]) && h[k] > 0.0))
+      return fail(PGO_EINVAL, "proximal weights h1..h4 must be finite and > 0");
+  if (o.precision != PGO_FP64 && o.precision != PGO_FP32)
+    return fail(PGO_EINVAL, "precision must be PGO_FP64 or PGO_FP32");
+  if (o.schedule < PGO_SCHED_AUTO || o.schedule > PGO_SCHED_GRAPH)
+    return fail(PGO_EINVAL, "unknown schedule");
+  if (o.block != 0 && (o.block < 64 || o.block > 1024 || o.block % 64 != 0))
+    return fail(PGO_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
+  return PGO_OK;
+}
+
+// Validates everything that can be checked on the host.  Rotations are
+// checked on the device during preparation.
+pgo_status check_inputs(int32_t G, const int64_t* voff, const int64_t* eoff, const double* R0,
+                        const double* t0, const int32_t* ei, const int32_t* ej, const double* Rm,
+                        const double* tm, const double* kappa, const double* tau) {
+  if (G < 1) return fail(PGO_EINVAL, "need at least one graph");
+  if (voff[0] != 0 || eoff[0] != 0) return fail(PGO_EINVAL, "voff[0] and eoff[0] must be 0");
+  for (int32_t g = 0; g < G; ++g) {
+    if (voff[g + 1] - voff[g] < 1)
+      return fail(PGO_EINVAL, "graph " + std::to_string(g) + " has no pose (n >= 1 required)");
+    if (eoff[g + 1] < eoff[g])
+      return fail(PGO_EINVAL, "eoff must be nondecreasing (graph " + std::to_string(g) + ")");
+  }
+  const int64_t n = voff[G], m = eoff[G];
+  if (n >= INT32_MAX) return fail(PGO_EINVAL, "too many poses (n must be < 2^31 - 1)");
+  if (m >= INT32_MAX) return fail(PGO_EINVAL, "too many edges (m must be < 2^31 - 1)");
+  if (m > 0 && (!ei || !ej || !Rm || !tm || !kappa || !tau))
+    return fail(PGO_EINVAL, "edge arrays must not be NULL");
+  if (!R0 || !t0) return fail(PGO_EINVAL, "R0 and t0 must not be NULL");
+  if (!finite_all(R0, size_t(9 * n)) || !finite_all(t0, size_t(3 * n)))
+    return fail(PGO_EINVAL, "initial poses contain a non-finite value");
+  if (m > 0 && (!finite_all(Rm, size_t(9 * m)) || !finite_all(tm, size_t(3 * m))))
+    return fail(PGO_EINVAL, "measurements contain a non-finite value");
+  for (int32_t g = 0; g < G; ++g) {
+    const int64_t ng = voff[g + 1] - voff[g];
+    for (int64_t e = eoff[g]; e < eoff[g + 1]; ++e) {
+      if (ei[e] < 0 || ei[e] >= ng || ej[e] < 0 || ej[e] >= ng)
+        return fail(PGO_EINVAL, "edge " + std::to_string(e) + " has an index out of range");
+      if (ei[e] == ej[e]) return fail(PGO_EINVAL, "edge " + std::to_string(e) + " is a self-loop");
+      if (!(std::isfinite(kappa[e]) && kappa[e] > 0.0) || !(std::isfinite(tau[e]) && tau[e] > 0.0))
+        return fail(PGO_EINVAL, "edge " + std::to_string(e) + " has kappa or tau not finite and > 0");
+    }
+  }
+  return PGO_OK;
+}
+
+pgo_status build_chunks(pgo_graph* g) {
+  std::vector<int64_t> eb, ee, vb, ve;
+  std::vector<int32_t> goe(g->G + 1, 0), gov(g->G + 1, 0);
+  for (int32_t k = 0; k < g->G; ++k) {
+    for (int64_t a = g->eoff_h[k]; a < g->eoff_h[k + 1]; a += kChunk) {
+      eb.push_back(a);
+      ee.push_back(std::min(a + kChunk, g->eoff_h[k + 1]));
+    }
+    goe[k + 1] = int32_t(eb.size());
+    for (int64_t a = g->voff_h[k]; a < g->voff_h[k + 1]; a += kChunk) {
+      vb.push_back(a);
+      ve.push_back(std::min(a + kChunk, g->voff_h[k + 1]));
+    }
+    gov[k + 1] = int32_t(vb.size());
+  }
+  g->n_ech = int(eb.size());
+  g->n_vch = int(vb.size());
+  pgo_status s;
+  if ((s = upload(g, &g->ec_beg, eb.data(), eb.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->ec_end, ee.data(), ee.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->vc_beg, vb.data(), vb.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->vc_end, ve.data(), ve.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->g_ec_off, goe.data(), goe.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->g_vc_off, gov.data(), gov.size())) != PGO_OK) return s;
+  if ((s = dalloc(g, &g->part_e, size_t(std::max(1, g->n_ech)))) != PGO_OK) return s;
+  if ((s = dalloc(g, &g->part_v, size_t(7) * std::max(1, g->n_vch))) != PGO_OK) return s;
+  if ((s = dalloc(g, &g->red_out, size_t(kRedVals) * g->G)) != PGO_OK) return s;
+  return PGO_OK;
+}
+
+template <typename T>
+pgo_status alloc_precision(pgo_graph* g) {
+  const size_t n = size_t(g->n), m = size_t(g->m);
+  pgo_status s;
+  void** vec4[] = {&g->p, &g->q, &g->lam, &g->t, &g->s, &g->z,
+                   &g->q_prev, &g->lam_prev, &g->t_prev, &g->s_prev, &g->z_prev};
+  for (void** v : vec4)
+    if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * n)) != PGO_OK) return s;
+  void** e4[] = {&g->o_tt, &g->o_w, &g->i_tt, &g->i_w};
+  for (void** v : e4)
+    if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * m)) != PGO_OK) return s;
+  void** c1[] = {&g->cQ, &g->cT, &g->cS};
+  for (void** v : c1)
+    if ((s = dalloc_bytes(g, v, sizeof(T) * n)) != PGO_OK) return s;
+  return PGO_OK;
+}
+
+template <typename T>
+pgo_status prepare_precision(pgo_graph* g, const double* t0_dev) {
+  hipStream_t st = g->stream;
+  HIPCHK(launch_fill_edges<T>(g->o_perm, g->ej, g->qe, g->tm, g->kappa, g->tau, g->m, g->o_nbr,
+                              static_cast<P4<T>*>(g->o_tt), static_cast<Q4<T>*>(g->o_w), st));
+  HIPCHK(launch_fill_edges<T>(g->i_perm, g->ei, g->qe, g->tm, g->kappa, g->tau, g->m, g->i_nbr,
+                              static_cast<P4<T>*>(g->i_tt), static_cast<Q4<T>*>(g->i_w), st));
+  HIPCHK(launch_vertex_consts<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->tm,
+                                 g->kappa, g->tau, static_cast<T*>(g->cQ),
+                                 static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
+  HIPCHK(launch_init_state<T>(view<T>(g), g->p0, t0_dev, st));
+  return PGO_OK;
+}
+
+pgo_status sort_edges(pgo_graph* g, const int32_t* keys, int32_t* perm, int32_t* ptr,
+                      int32_t* iota, int32_t* keys_sorted, void** tmp, size_t* tmp_bytes) {
+  if (g->m > 0) {
+    size_t need = 0;
+    HIPCHK(sort_by_key(keys, perm, g->m, int32_t(g->n), iota, nullptr, &need, keys_sorted,
+                       g->stream));
+    if (need > *tmp_bytes) {
+      dfree(g, *tmp);
+      *tmp = nullptr;
+      pgo_status s = dalloc_bytes(g, tmp, need);
+      if (s != PGO_OK) return s;
+      *tmp_bytes = need;
+    }
+    size_t have = *tmp_bytes;
+    HIPCHK(sort_by_key(keys, perm, g->m, int32_t(g->n), iota, *tmp, &have, keys_sorted, g->stream));
+  }
+  HIPCHK(launch_ptr_from_sorted(keys_sorted, g->m, int32_t(g->n), ptr, g->stream));
+  return PGO_OK;
+}
+
+pgo_status first_bad(pgo_graph* g, const uint8_t* flags_dev, int64_t count, int64_t* idx) {
+  *idx = -1;
+  if (count <= 0) return PGO_OK;
+  std::vector<uint8_t> h(static_cast<size_t>(count));
+  HIPCHK(hipMemcpyAsync(h.data(), flags_dev, size_t(count), hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  for (int64_t i = 0; i < count; ++i)
+    if (h[size_t(i)]) {
+      *idx = i;
+      break;
+    }
+  return PGO_OK;
+}
+
+void choose_default_schedule(pgo_graph* g) {
+  const int req = g->opt.schedule;
+  const bool graph_ok = g->max_n <= PGO_GRAPH_SCHED_MAX_N;
+  if (req == PGO_SCHED_GRAPH && graph_ok)
+    g->sched = PGO_SCHED_GRAPH;
+  else if (req == PGO_SCHED_PHASE || !graph_ok)
+    g->sched = PGO_SCHED_PHASE;
+  else  // auto: one workgroup per graph when graphs are small or numerous
+    g->sched = (g->max_n <= 8192 && (g->G >= 256 || g->n <= 16384)) ? PGO_SCHED_GRAPH
+                                                                      : PGO_SCHED_PHASE;
+  if (g->opt.block) {
+    g->block_phase = g->opt.block;
+    g->block_graph = g->opt.block;
+  } else {
+    g->block_phase = 256;
+    g->block_graph = g->max_n >= 2048 ? 512 : 256;
+  }
+}
+
+pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const int64_t* eoff,
+                       const double* R0, const double* t0, const int32_t* ei, const int32_t* ej,
+                       const double* Rm, const double* tm, const double* kappa, const double* tau,
+                       const pgo_options* opt_in) {
+  if (!out) return fail(PGO_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  pgo_options opt;
+  pgo_default_options(&opt);
+  if (opt_in) opt = *opt_in;
+  pgo_status s = check_options(opt);
+  if (s != PGO_OK) return s;
+  if (!voff || !eoff) return fail(PGO_EINVAL, "voff and eoff must not be NULL");
+  s = check_inputs(G, voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, tau);
+  if (s != PGO_OK) return s;
+
+  int ndev = 0;
+  HIPCHK(hipGetDeviceCount(&ndev));
+  if (opt.device < 0 || opt.device >= ndev)
+    return fail(PGO_EINVAL, "device " + std::to_string(opt.device) + " does not exist");
+  HIPCHK(hipSetDevice(opt.device));
+
+  pgo_graph* g = new pgo_graph();
+  g->device = opt.device;
+  g->opt = opt;
+  g->G = G;
+  g->n = voff[G];
+  g->m = eoff[G];
+  g->voff_h.assign(voff, voff + G + 1);
+  g->eoff_h.assign(eoff, eoff + G + 1);
+  for (int32_t k = 0; k < G; ++k) g->max_n = std::max<int32_t>(g->max_n, int32_t(voff[k + 1] - voff[k]));
+  auto bail = [&](pgo_status st) {
+    pgo_destroy(g);
+    return st;
+  };
+  hipError_t he = hipStreamCreateWithFlags(&g->own_stream, hipStreamNonBlocking);
+  if (he != hipSuccess) return bail(hip_fail(he, "hipStreamCreate"));
+  g->stream = g->own_stream;
+
+  const int64_t n = g->n, m = g->m;
+  // global edge indices
+  std::vector<int32_t> gei(static_cast<size_t>(m)), gej(static_cast<size_t>(m));
+  for (int32_t k = 0; k < G; ++k)
+    for (int64_t e = eoff[k]; e < eoff[k + 1]; ++e) {
+      gei[size_t(e)] = int32_t(ei[e] + voff[k]);
+      gej[size_t(e)] = int32_t(ej[e] + voff[k]);
+    }
+  std::vector<int32_t> voff32(static_cast<size_t>(G) + 1);
+  for (int32_t k = 0; k <= G; ++k) voff32[size_t(k)] = int32_t(voff[k]);
+  std::vector<int32_t> order(static_cast<size_t>(G));
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return (voff[a + 1] - voff[a]) + (eoff[a + 1] - eoff[a]) >
+           (voff[b + 1] - voff[b]) + (eoff[b + 1] - eoff[b]);
+  });
+
+  double *R0d = nullptr, *t0d = nullptr, *Rmd = nullptr;
+  uint8_t* bad = nullptr;
+  if ((s = upload(g, &g->ei, gei.data(), size_t(m))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->ej, gej.data(), size_t(m))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->tm, tm, size_t(3 * m))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->kappa, kappa, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->tau, tau, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &R0d, R0, size_t(9 * n))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &t0d, t0, size_t(3 * n))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &Rmd, Rm, size_t(9 * m))) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->voff32, voff32.data(), voff32.size())) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->order, order.data(), order.size())) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->p0, size_t(n))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->qe, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &bad, size_t(std::max(n, m)))) != PGO_OK) return bail(s);
+
+  // rotations -> quaternions (with validity flags)
+  he = launch_rot_to_quat(R0d, n, g->p0, 1, bad, g->stream);
+  if (he != hipSuccess) return bail(hip_fail(he, "rot_to_quat"));
+  int64_t badi = -1;
+  if ((s = first_bad(g, bad, n, &badi)) != PGO_OK) return bail(s);
+  if (badi >= 0)
+    return bail(fail(PGO_EINVAL, "initial rotation " + std::to_string(badi) +
+                                     " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
+  he = launch_rot_to_quat(Rmd, m, g->qe, 0, bad, g->stream);
+  if (he != hipSuccess) return bail(hip_fail(he, "rot_to_quat"));
+  if ((s = first_bad(g, bad, m, &badi)) != PGO_OK) return bail(s);
+  if (badi >= 0)
+    return bail(fail(PGO_EINVAL, "measured rotation of edge " + std::to_string(badi) +
+                                     " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
+  he = launch_align(g->p0, g->qe, g->ei, g->ej, m, g->stream);
+  if (he != hipSuccess) return bail(hip_fail(he, "align"));
+  dfree(g, R0d);
+  dfree(g, Rmd);
+  dfree(g, bad);
+
+  // CSR by tail, CSC by head
+  int32_t *iota = nullptr, *keys_sorted = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0;
+  if ((s = dalloc(g, &g->o_ptr, size_t(n + 1))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->i_ptr, size_t(n + 1))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->o_perm, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->i_perm, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->o_nbr, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->i_nbr, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &iota, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &keys_sorted, size_t(m))) != PGO_OK) return bail(s);
+  if ((s = sort_edges(g, g->ei, g->o_perm, g->o_ptr, iota, keys_sorted, &tmp, &tmp_bytes)) != PGO_OK)
+    return bail(s);
+  if ((s = sort_edges(g, g->ej, g->i_perm, g->i_ptr, iota, keys_sorted, &tmp, &tmp_bytes)) != PGO_OK)
+    return bail(s);
+
+  if (opt.precision == PGO_FP64) {
+    if ((s = alloc_precision<double>(g)) != PGO_OK) return bail(s);
+    if ((s = prepare_precision<double>(g, t0d)) != PGO_OK) return bail(s);
+  } else {
+    if ((s = alloc_precision<float>(g)) != PGO_OK) return bail(s);
+    if ((s = prepare_precision<float>(g, t0d)) != PGO_OK) return bail(s);
+  }
+  if ((s = build_chunks(g)) != PGO_OK) return bail(s);
+  he = hipStreamSynchronize(g->stream);
+  if (he != hipSuccess) return bail(hip_fail(he, "prepare"));
+  dfree(g, iota);
+  dfree(g, keys_sorted);
+  dfree(g, tmp);
+  dfree(g, t0d);
+  choose_default_schedule(g);
+  *out = g;
+  return PGO_OK;
+}
+
+template <typename T>
+pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block) {
+  SweepParams sp{beta, gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4};
+  const DevGraph<T> d = view<T>(g);
+  if (sched == PGO_SCHED_GRAPH) {
+    HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->stream));
+    return PGO_OK;
+  }
+  // per-phase launches, captured once into a HIP graph per (k, beta, gamma, block)
+  if (k == 1) {
+    HIPCHK(launch_phase_sweeps<T>(d, k, sp, block, g->stream));
+    return PGO_OK;
+  }
+  if (!(g->gexec && g->g_k == k && g->g_beta == beta && g->g_gamma == gamma && g->g_block == block)) {
+    if (g->gexec) {
+      (void)hipGraphExecDestroy(g->gexec);
+      g->gexec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = launch_phase_sweeps<T>(d, k, sp, block, g->stream);
+    const hipError_t ce = hipStreamEndCapture(g->stream, &graph);
+    if (le != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(le, "launch_phase_sweeps (capture)");
+    }
+    if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+    const hipError_t ie = hipGraphInstantiate(&g->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ie != hipSuccess) {
+      g->gexec = nullptr;
+      return hip_fail(ie, "hipGraphInstantiate");
+    }
+    g->g_k = k;
+    g->g_beta = beta;
+    g->g_gamma = gamma;
+    g->g_block = block;
+  }
+  HIPCHK(hipGraphLaunch(g->gexec, g->stream));
+  return PGO_OK;
+}
+
+pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block) {
+  pgo_status s = g->opt.precision == PGO_FP64 ? run_sweeps<double>(g, k, beta, gamma, sched, block)
+                                              : run_sweeps<float>(g, k, beta, gamma, sched, block);
+  if (s == PGO_OK) {
+    g->have_prev = true;
+    g->last_beta = beta;
+  }
+  return s;
+}
+
+pgo_status reduce(pgo_graph* g, std::vector<double>& out) {
+  HIPCHK(hipSetDevice(g->device));
+  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau};
+  hipError_t he;
+  if (g->opt.precision == PGO_FP64)
+    he = launch_reduce<double>(view<double>(g), e, g->have_prev, nullptr, g->ec_beg, g->ec_end,
+                               g->n_ech, nullptr, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
+                               g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
+  else
+    he = launch_reduce<float>(view<float>(g), e, g->have_prev, nullptr, g->ec_beg, g->ec_end,
+                              g->n_ech, nullptr, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
+                              g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
+  if (he != hipSuccess) return hip_fail(he, "reduce");
+  out.resize(size_t(kRedVals) * g->G);
+  HIPCHK(hipMemcpyAsync(out.data(), g->red_out, out.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  for (double v : out)
+    if (!std::isfinite(v)) return fail(PGO_ENUMERIC, "the state contains a non-finite value");
+  return PGO_OK;
+}
+
+pgo_status ensure_iobuf(pgo_graph* g) {
+  if (g->iobuf) return PGO_OK;
+  return dalloc(g, &g->iobuf, size_t(21) * g->n);
+}
+
+}  // namespace
+
+extern "C" {
+
+void pgo_default_options(pgo_options* o) {
+  if (!o) return;
+  o->h1 = 1.0;
+  o->h2 = 1e-3;
+  o->h3 = 1e-3;
+  o->h4 = 1e-3;
+  o->precision = PGO_FP64;
+  o->schedule = PGO_SCHED_AUTO;
+  o->block = 0;
+  o->device = 0;
+}
+
+const char* pgo_last_error(void) { return g_err.c_str(); }
+
+pgo_status pgo_create(pgo_graph** out, int32_t n, const double* R0, const double* t0, int64_t m,
+                      const int32_t* ei, const int32_t* ej, const double* Rm, const double* tm,
+                      const double* kappa, const double* tau, const pgo_options* opt) {
+  if (n < 1) return fail(PGO_EINVAL, "n must be >= 1");
+  if (m < 0) return fail(PGO_EINVAL, "m must be >= 0");
+  const int64_t voff[2] = {0, n}, eoff[2] = {0, m};
+  return create_impl(out, 1, voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, tau, opt);
+}
+
+pgo_status pgo_create_batched(pgo_graph** out, int32_t G, const int64_t* voff,
+                              const int64_t* eoff, const double* R0, const double* t0,
+                              const int32_t* ei, const int32_t* ej, const double* Rm,
+                              const double* tm, const double* kappa, const double* tau,
+                              const pgo_options* opt) {
+  return create_impl(out, G, voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, tau, opt);
+}
+
+pgo_status pgo_set_stream(pgo_graph* g, void* hip_stream) {
+  if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  g->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : g->own_stream;
+  return PGO_OK;
+}
+
+pgo_status pgo_iterate(pgo_graph* g, int32_t k, double beta, double gamma) {
+  if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  if (k < 0) return fail(PGO_EINVAL, "k must be >= 0");
+  if (!(std::isfinite(beta) && beta > 0.0)) return fail(PGO_EINVAL, "beta must be finite and > 0");
+  if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
+  if (k == 0) return PGO_OK;
+  HIPCHK(hipSetDevice(g->device));
+  const int block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
+  return iterate_with(g, k, beta, gamma, g->sched, block);
+}
+
+pgo_status pgo_cost(pgo_graph* g, double* F) {
+  if (!g || !F) return fail(PGO_EINVAL, "NULL argument");
+  std::vector<double> r;
+  pgo_status s = reduce(g, r);
+  if (s != PGO_OK) return s;
+  for (int32_t k = 0; k < g->G; ++k) F[k] = r[size_t(kRedVals) * k];
+  return PGO_OK;
+}
+
+pgo_status pgo_residuals(pgo_graph* g, double* out) {
+  if (!g || !out) return fail(PGO_EINVAL, "NULL argument");
+  std::vector<double> r;
+  pgo_status s = reduce(g, r);
+  if (s != PGO_OK) return s;
+  const double b = g->last_beta;
+  for (int32_t k = 0; k < g->G; ++k) {
+    const double* v = &r[size_t(kRedVals) * k];
+    double* o = out + 6 * size_t(k);
+    o[0] = std::sqrt(v[1]);
+    o[1] = std::sqrt(v[2]);
+    o[2] = (v[3] + v[4]) / b + b * (v[5] + v[6]);
+    o[3] = b * std::sqrt(v[5]);
+    o[4] = b * std::sqrt(v[7]);
+    o[5] = v[0];
+  }
+  return PGO_OK;
+}
+
+pgo_status pgo_get_poses(pgo_graph* g, double* R, double* t) {
+  if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  if (!R && !t) return PGO_OK;
+  HIPCHK(hipSetDevice(g->device));
+  pgo_status s = ensure_iobuf(g);
+  if (s != PGO_OK) return s;
+  double* dR = R ? g->iobuf : nullptr;
+  double* dt = t ? g->iobuf + 9 * g->n : nullptr;
+  hipError_t he = g->opt.precision == PGO_FP64
+                      ? launch_poses<double>(view<double>(g), dR, dt, g->stream)
+                      : launch_poses<float>(view<float>(g), dR, dt, g->stream);
+  if (he != hipSuccess) return hip_fail(he, "poses");
+  if (R) HIPCHK(hipMemcpyAsync(R, dR, sizeof(double) * 9 * g->n, hipMemcpyDeviceToHost, g->stream));
+  if (t) HIPCHK(hipMemcpyAsync(t, dt, sizeof(double) * 3 * g->n, hipMemcpyDeviceToHost, g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return PGO_OK;
+}
+
+pgo_status pgo_get_state(pgo_graph* g, double* state) {
+  if (!g || !state) return fail(PGO_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(g->device));
+  pgo_status s = ensure_iobuf(g);
+  if (s != PGO_OK) return s;
+  hipError_t he = g->opt.precision == PGO_FP64
+                      ? launch_state_io<double>(view<double>(g), g->iobuf, 0, g->stream)
+                      : launch_state_io<float>(view<float>(g), g->iobuf, 0, g->stream);
+  if (he != hipSuccess) return hip_fail(he, "state_io");
+  HIPCHK(hipMemcpyAsync(state, g->iobuf, sizeof(double) * 21 * g->n, hipMemcpyDeviceToHost,
+                        g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return PGO_OK;
+}
+
+pgo_status pgo_set_state(pgo_graph* g, const double* state) {
+  if (!g || !state) return fail(PGO_EINVAL, "NULL argument");
+  HIPCHK(hipSetDevice(g->device));
+  pgo_status s = ensure_iobuf(g);
+  if (s != PGO_OK) return s;
+  HIPCHK(hipMemcpyAsync(g->iobuf, state, sizeof(double) * 21 * g->n, hipMemcpyHostToDevice,
+                        g->stream));
+  hipError_t he = g->opt.precision == PGO_FP64
+                      ? launch_state_io<double>(view<double>(g), g->iobuf, 1, g->stream)
+                      : launch_state_io<float>(view<float>(g), g->iobuf, 1, g->stream);
+  if (he != hipSuccess) return hip_fail(he, "state_io");
+  HIPCHK(hipStreamSynchronize(g->stream));
+  g->have_prev = false;
+  return PGO_OK;
+}
+
+pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat0) {
+  if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  HIPCHK(hipSetDevice(g->device));
+  if (edge_quat && g->m)
+    HIPCHK(hipMemcpyAsync(edge_quat, g->qe, sizeof(double) * 4 * g->m, hipMemcpyDeviceToHost,
+                          g->stream));
+  if (vertex_quat0)
+    HIPCHK(hipMemcpyAsync(vertex_quat0, g->p0, sizeof(double) * 4 * g->n, hipMemcpyDeviceToHost,
+                          g->stream));
+  HIPCHK(hipStreamSynchronize(g->stream));
+  return PGO_OK;
+}
+
+pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
+                    int32_t* schedule, int32_t* block) {
+  if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  if (n) *n = g->n;
+  if (m) *m = g->m;
+  if (G) *G = g->G;
+  if (precision) *precision = g->opt.precision;
+  if (schedule) *schedule = g->sched;
+  if (block) *block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
+  return PGO_OK;
+}
+
+pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps) {
+  if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  if (sweeps < 1) return fail(PGO_EINVAL, "sweeps must be >= 1");
+  if (!(std::isfinite(beta) && beta > 0.0)) return fail(PGO_EINVAL, "beta must be finite and > 0");
+  if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
+  HIPCHK(hipSetDevice(g->device));
+  std::vector<double> saved(size_t(21) * g->n);
+  pgo_status s = pgo_get_state(g, saved.data());
+  if (s != PGO_OK) return s;
+  struct Cand {
+    int sched, block;
+  };
+  std::vector<Cand> cands;
+  for (int b : {64, 128, 256, 512}) cands.push_back({PGO_SCHED_PHASE, b});
+  if (g->max_n <= PGO_GRAPH_SCHED_MAX_N)
+    for (int b : {128, 256, 512, 1024}) cands.push_back({PGO_SCHED_GRAPH, b});
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  Cand pick{g->sched, g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase};
+  for (const Cand& c : cands) {
+    if ((s = pgo_set_state(g, saved.data())) != PGO_OK) break;
+    if ((s = iterate_with(g, sweeps, beta, gamma, c.sched, c.block)) != PGO_OK) break;  // warm-up
+    if ((s = pgo_set_state(g, saved.data())) != PGO_OK) break;
+    (void)hipEventRecord(e0, g->stream);
+    if ((s = iterate_with(g, sweeps, beta, gamma, c.sched, c.block)) != PGO_OK) break;
+    (void)hipEventRecord(e1, g->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      pick = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != PGO_OK) return s;
+  g->sched = pick.sched;
+  if (pick.sched == PGO_SCHED_GRAPH)
+    g->block_graph = pick.block;
+  else
+    g->block_phase = pick.block;
+  return pgo_set_state(g, saved.data());
+}
+
+void pgo_destroy(pgo_graph* g) {
+  if (!g) return;
+  (void)hipSetDevice(g->device);
+  if (g->stream) (void)hipStreamSynchronize(g->stream);
+  if (g->gexec) (void)hipGraphExecDestroy(g->gexec);
+  for (void* p : g->allocs) (void)hipFree(p);
+  if (g->own_stream) (void)hipStreamDestroy(g->own_stream);
+  delete g;
+}
+
+}  // extern "C"

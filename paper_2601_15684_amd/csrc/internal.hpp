@@ -1,0 +1,115 @@
+// Internal interfaces between the host side of the library (api.cpp) and the
+// kernel translation units.  Nothing here is part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qmath.hpp"
+
+namespace pgo {
+
+// Device view of one handle's graph and state for precision T.
+//
+// Edges are stored twice, structure-of-arrays, in the order "by tail" (out,
+// CSR) and "by head" (in, CSC); inside one vertex the edges keep the
+// caller's edge order.  Each edge record is
+//   nbr  the other end (head for out-order, tail for in-order)
+//   tt   (tau t~_e, tau_e)
+//   w    kappa_e q~_e
+// so the per-edge terms are linear in the stored quantities.
+// Vertex constants (depend only on the edges):
+//   cQ_i = 2 sum_out (tau_e |t~_e|^2 + kappa_e)   (A2 = (cQ + beta + H2) I)
+//   cT_i = 2 sum_in  tau_e                        (A3 = (cT + beta + H3) I)
+//   cS_i = 2 sum_out tau_e                        (A4 = (cS + beta + H4) I)
+template <typename T>
+struct DevGraph {
+  int32_t n;
+  const int32_t* o_ptr;
+  const int32_t* o_nbr;
+  const P4<T>* o_tt;
+  const Q4<T>* o_w;
+  const int32_t* i_ptr;
+  const int32_t* i_nbr;
+  const P4<T>* i_tt;
+  const Q4<T>* i_w;
+  const T* cQ;
+  const T* cT;
+  const T* cS;
+  Q4<T>* p;
+  Q4<T>* q;
+  Q4<T>* lam;
+  P4<T>* t;
+  P4<T>* s;
+  P4<T>* z;
+  // values before the last sweep of an iterate call (residual history)
+  Q4<T>* q_prev;
+  Q4<T>* lam_prev;
+  P4<T>* t_prev;
+  P4<T>* s_prev;
+  P4<T>* z_prev;
+};
+
+struct SweepParams {
+  double beta, gamma, h1, h2, h3, h4;
+};
+
+// Launchers (sweep.hip).  Every launcher checks its own configuration and
+// returns the HIP status of the launch.
+template <typename T>
+hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& sp, int block,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
+                               int G, int k, const SweepParams& sp, int block, hipStream_t st);
+
+// Boundary preparation (prep.hip), FP64.
+// bad[i] = 1 where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
+hipError_t launch_rot_to_quat(const double* R, int64_t count, Q4<double>* out, int canonical,
+                              uint8_t* bad, hipStream_t st);
+hipError_t launch_align(const Q4<double>* pv, Q4<double>* qe, const int32_t* ei,
+                        const int32_t* ej, int64_t m, hipStream_t st);
+// Stable sort of edge ids by key (tail or head).  Call once with tmp = nullptr
+// to get the temporary size, then with a buffer of that size.
+hipError_t sort_by_key(const int32_t* keys, int32_t* perm, int64_t m, int32_t n, int32_t* iota,
+                       void* tmp, size_t* tmp_bytes, int32_t* keys_sorted, hipStream_t st);
+hipError_t launch_ptr_from_sorted(const int32_t* keys_sorted, int64_t m, int32_t n, int32_t* ptr,
+                                  hipStream_t st);
+template <typename T>
+hipError_t launch_fill_edges(const int32_t* perm, const int32_t* nbr_src, const Q4<double>* qe,
+                             const double* tm, const double* kappa, const double* tau, int64_t m,
+                             int32_t* nbr, P4<T>* tt, Q4<T>* w, hipStream_t st);
+template <typename T>
+hipError_t launch_vertex_consts(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
+                                const int32_t* i_ptr, const int32_t* i_perm, const double* tm,
+                                const double* kappa, const double* tau, T* cQ, T* cT, T* cS,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_init_state(const DevGraph<T>& g, const Q4<double>* p0, const double* t0,
+                             hipStream_t st);
+template <typename T>
+hipError_t launch_state_io(const DevGraph<T>& g, double* buf, int to_device, hipStream_t st);
+template <typename T>
+hipError_t launch_poses(const DevGraph<T>& g, double* R, double* t, hipStream_t st);
+
+// FP64 reductions (reduce.hip).  Items are split into chunks that never cross
+// a graph boundary; chunk c covers [cbeg[c], cend[c]) of graph cgraph[c].
+// Partial sums of a chunk are reduced in a fixed order, then each graph sums
+// its chunks in order, so results are deterministic.
+struct EdgeF64 {  // caller-order FP64 copy of the prepared edges for the cost
+  const int32_t* ei;
+  const int32_t* ej;
+  const Q4<double>* q;
+  const double* tm;
+  const double* kappa;
+  const double* tau;
+};
+constexpr int kRedVals = 8;  // cost, |p-q|^2, |t-s|^2, |dl|^2, |dz|^2, |dq|^2, |dt|^2, |ds|^2
+template <typename T>
+hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
+                         const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,
+                         int n_echunks, const int32_t* vc_graph, const int64_t* vc_beg,
+                         const int64_t* vc_end, int n_vchunks, double* partial_e,
+                         double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
+                         int G, double* out, hipStream_t st);
+
+}  // namespace pgo

@@ -1,0 +1,140 @@
+// FP64 reductions per graph: the cost of model (1) at (p, t) and the
+// residual sums behind App. E.1's iteration residual.  Work is cut into
+// chunks that never straddle two graphs; each workgroup reduces one chunk
+// with a fixed-shape tree, then one thread per graph adds its chunks in
+// order.  No atomics, so every run gives the same bits.
+#include "internal.hpp"
+
+namespace pgo {
+
+namespace {
+
+constexpr int kRB = 256;
+constexpr int kVVals = 7;  // |p-q|^2 |t-s|^2 |dl|^2 |dz|^2 |dq|^2 |dt|^2 |ds|^2
+
+template <int K>
+__device__ void block_sum(double (&v)[K], double (*sh)[kRB]) {
+  for (int k = 0; k < K; ++k) sh[k][threadIdx.x] = v[k];
+  __syncthreads();
+  for (int w = kRB / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < K; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  for (int k = 0; k < K; ++k) v[k] = sh[k][0];
+}
+
+// cost term of edge e (model (1), Sigma1 = tau I_4, Sigma2 = kappa I_4)
+template <typename T>
+__device__ double edge_cost(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
+  const int i = E.ei[e], j = E.ej[e];
+  const Q4<double> pi = cvt<double>(g.p[i]), pj = cvt<double>(g.p[j]);
+  const P4<T> ti = g.t[i], tj = g.t[j];
+  const V3<double> tt = {E.tm[3 * e], E.tm[3 * e + 1], E.tm[3 * e + 2]};
+  const Q4<double> rot = qmul(qmul_vp(pi, tt), qconj(pi));  // p_i [0, t~] p_i^*
+  const double r0 = -rot.w;
+  const double r1 = (double(tj.x) - double(ti.x)) - rot.x;
+  const double r2 = (double(tj.y) - double(ti.y)) - rot.y;
+  const double r3 = (double(tj.z) - double(ti.z)) - rot.z;
+  const Q4<double> a = qmul(qmul(qconj(pj), pi), E.q[e]);  // p_j^* p_i q~
+  const double a0 = a.w - 1.0;
+  return E.tau[e] * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3) +
+         E.kappa[e] * (a0 * a0 + a.x * a.x + a.y * a.y + a.z * a.z);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRB) k_red_edges(DevGraph<T> g, EdgeF64 E,
+                                                    const int64_t* __restrict__ beg,
+                                                    const int64_t* __restrict__ end,
+                                                    double* __restrict__ partial) {
+  __shared__ double sh[1][kRB];
+  double v[1] = {0.0};
+  const int c = blockIdx.x;
+  for (int64_t e = beg[c] + threadIdx.x; e < end[c]; e += kRB) v[0] += edge_cost(g, E, e);
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) partial[c] = v[0];
+}
+
+template <typename T, typename V>
+__device__ __forceinline__ double d2(const V& a, const V& b) {
+  const double x = double(a.x) - double(b.x), y = double(a.y) - double(b.y),
+               z = double(a.z) - double(b.z);
+  return x * x + y * y + z * z;
+}
+
+template <typename T>
+__device__ __forceinline__ double d2q(const Q4<T>& a, const Q4<T>& b) {
+  const double w = double(a.w) - double(b.w);
+  return w * w + d2<T, Q4<T>>(a, b);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRB) k_red_vertices(DevGraph<T> g, int have_prev,
+                                                       const int64_t* __restrict__ beg,
+                                                       const int64_t* __restrict__ end,
+                                                       double* __restrict__ partial) {
+  __shared__ double sh[kVVals][kRB];
+  double v[kVVals] = {0, 0, 0, 0, 0, 0, 0};
+  const int c = blockIdx.x;
+  for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
+    v[0] += d2q(g.p[i], g.q[i]);
+    v[1] += d2<T, P4<T>>(g.t[i], g.s[i]);
+    if (have_prev) {
+      v[2] += d2q(g.lam[i], g.lam_prev[i]);
+      v[3] += d2<T, P4<T>>(g.z[i], g.z_prev[i]);
+      v[4] += d2q(g.q[i], g.q_prev[i]);
+      v[5] += d2<T, P4<T>>(g.t[i], g.t_prev[i]);
+      v[6] += d2<T, P4<T>>(g.s[i], g.s_prev[i]);
+    }
+  }
+  block_sum<kVVals>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kVVals; ++k) partial[kVVals * int64_t(c) + k] = v[k];
+}
+
+__global__ void k_red_finish(const double* __restrict__ pe, const double* __restrict__ pv,
+                             const int32_t* __restrict__ g_ec_off,
+                             const int32_t* __restrict__ g_vc_off, int G, double* __restrict__ out) {
+  const int gr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gr >= G) return;
+  double c = 0.0;
+  for (int k = g_ec_off[gr]; k < g_ec_off[gr + 1]; ++k) c += pe[k];
+  double v[kVVals] = {0, 0, 0, 0, 0, 0, 0};
+  for (int k = g_vc_off[gr]; k < g_vc_off[gr + 1]; ++k)
+    for (int q = 0; q < kVVals; ++q) v[q] += pv[kVVals * int64_t(k) + q];
+  out[kRedVals * int64_t(gr)] = c;
+  for (int q = 0; q < kVVals; ++q) out[kRedVals * int64_t(gr) + 1 + q] = v[q];
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
+                         const int32_t* /*ec_graph*/, const int64_t* ec_beg, const int64_t* ec_end,
+                         int n_echunks, const int32_t* /*vc_graph*/, const int64_t* vc_beg,
+                         const int64_t* vc_end, int n_vchunks, double* partial_e,
+                         double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
+                         int G, double* out, hipStream_t st) {
+  if (n_echunks > 0)
+    hipLaunchKernelGGL((k_red_edges<T>), dim3(n_echunks), dim3(kRB), 0, st, g, e, ec_beg, ec_end,
+                       partial_e);
+  if (n_vchunks > 0)
+    hipLaunchKernelGGL((k_red_vertices<T>), dim3(n_vchunks), dim3(kRB), 0, st, g, have_prev,
+                       vc_beg, vc_end, partial_v);
+  hipLaunchKernelGGL(k_red_finish, dim3((G + 255) / 256), dim3(256), 0, st, partial_e, partial_v,
+                     g_ec_off, g_vc_off, G, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_reduce<float>(const DevGraph<float>&, const EdgeF64&, int,
+                                         const int32_t*, const int64_t*, const int64_t*, int,
+                                         const int32_t*, const int64_t*, const int64_t*, int,
+                                         double*, double*, const int32_t*, const int32_t*, int,
+                                         double*, hipStream_t);
+template hipError_t launch_reduce<double>(const DevGraph<double>&, const EdgeF64&, int,
+                                          const int32_t*, const int64_t*, const int64_t*, int,
+                                          const int32_t*, const int64_t*, const int64_t*, int,
+                                          double*, double*, const int32_t*, const int32_t*, int,
+                                          double*, hipStream_t);
+
+}  // namespace pgo

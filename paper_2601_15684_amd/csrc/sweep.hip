@@ -1,0 +1,279 @@
+// The PRADMM sweep on gfx950: four vertex-parallel phases per iteration
+// (Alg. 1 steps 2-6), each a closed-form per-vertex update over the vertex's
+// incident edges (App. B, scalar Sigma):
+//
+//   P  v_i = 2 sum_out [0, s_i - t_j] (x) q_i (x) [0, tau t~_e]
+//          + 2 sum_in  q_l (x) (kappa q~_e) + beta q_i + lambda_i + H1 p_i
+//      p_i = v_i / |v_i|                       (= -b1/|b1|, App. B.1; p kept if v = 0)
+//   Q  q_i = (2 sum_out {[0, t_j - s_i] (x) p_i (x) [0, -tau t~_e]
+//                        + p_j (x) (kappa q~_e)^*} + beta p_i - lambda_i + H2 q_i)
+//            / (cQ_i + beta + H2)              (= A2^{-1} b2, App. B.2)
+//      lambda_i -= gamma beta (p_i - q_i)      (eq. 3e)
+//   T  t_i = (2 sum_in {tau s_l + Im(q_l (x) [0, tau t~_e] (x) p_l^*)}
+//            + beta s_i + z_i + H3 t_i) / (cT_i + beta + H3)     (App. B.3)
+//   S  s_i = (2 sum_out {tau t_j - Im(q_i (x) [0, tau t~_e] (x) p_i^*)}
+//            + beta t_i - z_i + H4 s_i) / (cS_i + beta + H4)     (App. B.4)
+//      z_i -= gamma beta (t_i - s_i)           (eq. 3f)
+//
+// Each fused product equals the paper's G-matrix expression by Lemma MW:
+// G1^T r = r^* q_i t~ (G1 = M(q_i) M(t~) D), G2^T 1 = q_l q~ (G2 = W(q~) W(q_l) D),
+// G3^T r = r p_i t~^*, G4^T 1 = p_j q~^*, G3^T G3 = |t~|^2 I, G4^T G4 = I.
+//
+// Inside a phase a vertex reads only values written by earlier phases, and
+// writes only its own slots, so all updates are in place and race-free.
+// Per-vertex sums run over the CSR/CSC segment in edge order, one thread per
+// vertex, with no atomics: results are deterministic and identical between
+// the per-phase launches and the per-graph persistent kernel.
+#include "internal.hpp"
+
+namespace pgo {
+
+template <typename A, typename T>
+__device__ __forceinline__ V3<A> v3a(const P4<T>& a) {
+  return {A(a.x), A(a.y), A(a.z)};
+}
+
+template <typename A>
+__device__ __forceinline__ void acc4(Q4<A>& s, const Q4<A>& t) {
+  s.w += t.w; s.x += t.x; s.y += t.y; s.z += t.z;
+}
+
+template <typename A>
+__device__ __forceinline__ A l1(const Q4<A>& t) {
+  return fabs(t.w) + fabs(t.x) + fabs(t.y) + fabs(t.z);
+}
+
+// Sum of the edge terms of the P phase, in accumulation type A.  mag collects
+// the L1 size of every term (used only by the FP32 cancellation check).
+template <typename A, typename T, bool kMag>
+__device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, A& mag) {
+  const Q4<A> qi = cvt<A>(g.q[i]);
+  const V3<A> si = v3a<A>(g.s[i]);
+  Q4<A> acc = {A(0), A(0), A(0), A(0)};
+  const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
+  for (int e = o0; e < o1; ++e) {
+    const int j = g.o_nbr[e];
+    const V3<A> tj = v3a<A>(g.t[j]);
+    const V3<A> u = v3a<A>(g.o_tt[e]);
+    const V3<A> mr = {si.x - tj.x, si.y - tj.y, si.z - tj.z};  // [0, r]^* = [0, s_i - t_j]
+    const Q4<A> term = qmul_vp(qmul_pv(mr, qi), u);
+    acc4(acc, term);
+    if (kMag) mag += l1(term);
+  }
+  const int n0 = g.i_ptr[i], n1 = g.i_ptr[i + 1];
+  for (int e = n0; e < n1; ++e) {
+    const int l = g.i_nbr[e];
+    const Q4<A> term = qmul(cvt<A>(g.q[l]), cvt<A>(g.i_w[e]));
+    acc4(acc, term);
+    if (kMag) mag += l1(term);
+  }
+  return acc;
+}
+
+template <typename A, typename T>
+__device__ __forceinline__ Q4<A> p_vector(const DevGraph<T>& g, int i, const Q4<A>& acc,
+                                          const SweepParams& sp) {
+  const Q4<A> qi = cvt<A>(g.q[i]), li = cvt<A>(g.lam[i]), pi = cvt<A>(g.p[i]);
+  const A b = A(sp.beta), h = A(sp.h1);
+  return {A(2) * acc.w + b * qi.w + li.w + h * pi.w, A(2) * acc.x + b * qi.x + li.x + h * pi.x,
+          A(2) * acc.y + b * qi.y + li.y + h * pi.y, A(2) * acc.z + b * qi.z + li.z + h * pi.z};
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_P(const DevGraph<T>& g, int i, const SweepParams& sp) {
+  constexpr bool kF32 = sizeof(T) == 4;
+  T mag = T(0);
+  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, i, mag);
+  const Q4<T> v = p_vector<T, T>(g, i, acc, sp);
+  const T nrm = sqrt(v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z);
+  if (kF32) {
+    // FP64 island: when the sum cancels, redo it in double.
+    const Q4<T> qi = g.q[i], li = g.lam[i], pi = g.p[i];
+    const T tot = T(2) * mag + T(sp.beta) * l1(qi) + l1(li) + T(sp.h1) * l1(pi);
+    if (!(nrm >= T(1e-3) * tot)) {
+      double dm = 0.0;
+      const Q4<double> dacc = p_edge_sum<double, T, false>(g, i, dm);
+      const Q4<double> dv = p_vector<double, T>(g, i, dacc, sp);
+      const double dn = sqrt(dv.w * dv.w + dv.x * dv.x + dv.y * dv.y + dv.z * dv.z);
+      if (dn > 0.0)
+        g.p[i] = Q4<T>{T(dv.w / dn), T(dv.x / dn), T(dv.y / dn), T(dv.z / dn)};
+      return;
+    }
+  }
+  if (nrm > T(0)) g.p[i] = Q4<T>{v.w / nrm, v.x / nrm, v.y / nrm, v.z / nrm};
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                         bool save) {
+  const Q4<T> pi = g.p[i], qi = g.q[i], li = g.lam[i];
+  const V3<T> si = v3(g.s[i]);
+  Q4<T> acc = {T(0), T(0), T(0), T(0)};
+  const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
+  for (int e = o0; e < o1; ++e) {
+    const int j = g.o_nbr[e];
+    const V3<T> tj = v3(g.t[j]);
+    const P4<T> u = g.o_tt[e];
+    const V3<T> r = {tj.x - si.x, tj.y - si.y, tj.z - si.z};
+    const V3<T> mu = {-u.x, -u.y, -u.z};  // [0, tau t~]^*
+    acc4(acc, qmul_vp(qmul_pv(r, pi), mu));
+    acc4(acc, qmul(g.p[j], qconj(g.o_w[e])));
+  }
+  const T b = T(sp.beta), h = T(sp.h2);
+  const T a = g.cQ[i] + b + h;
+  const Q4<T> qn = {(T(2) * acc.w + b * pi.w - li.w + h * qi.w) / a,
+                    (T(2) * acc.x + b * pi.x - li.x + h * qi.x) / a,
+                    (T(2) * acc.y + b * pi.y - li.y + h * qi.y) / a,
+                    (T(2) * acc.z + b * pi.z - li.z + h * qi.z) / a};
+  const T gb = T(sp.gamma * sp.beta);
+  if (save) {
+    g.q_prev[i] = qi;
+    g.lam_prev[i] = li;
+  }
+  g.q[i] = qn;
+  g.lam[i] = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x),
+                   li.y - gb * (pi.y - qn.y), li.z - gb * (pi.z - qn.z)};
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                         bool save) {
+  V3<T> acc = {T(0), T(0), T(0)};
+  const int n0 = g.i_ptr[i], n1 = g.i_ptr[i + 1];
+  for (int e = n0; e < n1; ++e) {
+    const int l = g.i_nbr[e];
+    const P4<T> u = g.i_tt[e];
+    const V3<T> sl = v3(g.s[l]);
+    const V3<T> c = im_mul_conj(qmul_vp(g.q[l], v3(u)), g.p[l]);  // Im(q_l [0,tau t~] p_l^*)
+    acc.x += u.u * sl.x + c.x;
+    acc.y += u.u * sl.y + c.y;
+    acc.z += u.u * sl.z + c.z;
+  }
+  const P4<T> ti = g.t[i], si = g.s[i], zi = g.z[i];
+  const T b = T(sp.beta), h = T(sp.h3);
+  const T a = g.cT[i] + b + h;
+  if (save) g.t_prev[i] = ti;
+  g.t[i] = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+                 (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
+                 (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                         bool save) {
+  const Q4<T> pi = g.p[i], qi = g.q[i];
+  V3<T> acc = {T(0), T(0), T(0)};
+  const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
+  for (int e = o0; e < o1; ++e) {
+    const int j = g.o_nbr[e];
+    const P4<T> u = g.o_tt[e];
+    const V3<T> tj = v3(g.t[j]);
+    const V3<T> c = im_mul_conj(qmul_vp(qi, v3(u)), pi);  // Im(q_i [0,tau t~] p_i^*)
+    acc.x += u.u * tj.x - c.x;
+    acc.y += u.u * tj.y - c.y;
+    acc.z += u.u * tj.z - c.z;
+  }
+  const P4<T> ti = g.t[i], si = g.s[i], zi = g.z[i];
+  const T b = T(sp.beta), h = T(sp.h4);
+  const T a = g.cS[i] + b + h;
+  const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
+                    (T(2) * acc.y + b * ti.y - zi.y + h * si.y) / a,
+                    (T(2) * acc.z + b * ti.z - zi.z + h * si.z) / a};
+  const T gb = T(sp.gamma * sp.beta);
+  if (save) {
+    g.s_prev[i] = si;
+    g.z_prev[i] = zi;
+  }
+  g.s[i] = pad3(sn);
+  g.z[i] = P4<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
+                 zi.z - gb * (ti.z - sn.z), T(0)};
+}
+
+// ---------------------------------------------------------------------------
+// one launch per phase
+// ---------------------------------------------------------------------------
+constexpr int kXcds = 8;
+
+// Workgroups are dispatched to the 8 XCDs round-robin; renumber them so each
+// XCD works on one contiguous range of vertices (neighbour gathers then hit
+// that XCD's own L2).  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int xcd = b % kXcds, local = b / kXcds;
+  const int per = nb / kXcds, rem = nb % kXcds;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+template <int PH, typename T>
+__global__ void k_phase(DevGraph<T> g, SweepParams sp, int save) {
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  if (PH == 0) vertex_P(g, i, sp);
+  if (PH == 1) vertex_Q(g, i, sp, save != 0);
+  if (PH == 2) vertex_T(g, i, sp, save != 0);
+  if (PH == 3) vertex_S(g, i, sp, save != 0);
+}
+
+template <typename T>
+hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& sp, int block,
+                               hipStream_t st) {
+  if (g.n <= 0 || k <= 0) return hipSuccess;
+  if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  const int nb = (g.n + block - 1) / block;
+  for (int it = 0; it < k; ++it) {
+    const int save = it == k - 1;
+    hipLaunchKernelGGL((k_phase<0, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    hipLaunchKernelGGL((k_phase<1, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    hipLaunchKernelGGL((k_phase<2, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    hipLaunchKernelGGL((k_phase<3, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// one persistent workgroup per graph: all k sweeps in one launch; the phase
+// barrier is the workgroup barrier, so no grid-wide synchronisation exists.
+// order[] lists graphs largest first (the hardware hands out workgroups in
+// index order, which makes this a longest-first greedy schedule).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_graph_sweeps(DevGraph<T> g, const int32_t* __restrict__ voff,
+                               const int32_t* __restrict__ order, int k, SweepParams sp) {
+  const int gr = order[blockIdx.x];
+  const int v0 = voff[gr], v1 = voff[gr + 1];
+  for (int it = 0; it < k; ++it) {
+    const bool save = it == k - 1;
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_P(g, i, sp);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_Q(g, i, sp, save);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_T(g, i, sp, save);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_S(g, i, sp, save);
+    __syncthreads();
+  }
+}
+
+template <typename T>
+hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
+                               int G, int k, const SweepParams& sp, int block, hipStream_t st) {
+  if (G <= 0 || k <= 0) return hipSuccess;
+  if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_graph_sweeps<T>), dim3(G), dim3(block), 0, st, g, voff, order, k, sp);
+  return hipGetLastError();
+}
+
+template hipError_t launch_phase_sweeps<float>(const DevGraph<float>&, int, const SweepParams&,
+                                               int, hipStream_t);
+template hipError_t launch_phase_sweeps<double>(const DevGraph<double>&, int,
+                                                const SweepParams&, int, hipStream_t);
+template hipError_t launch_graph_sweeps<float>(const DevGraph<float>&, const int32_t*,
+                                               const int32_t*, int, int, const SweepParams&, int,
+                                               hipStream_t);
+template hipError_t launch_graph_sweeps<double>(const DevGraph<double>&, const int32_t*,
+                                                const int32_t*, int, int, const SweepParams&, int,
+                                                hipStream_t);
+
+}  // namespace pgo

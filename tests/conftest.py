@@ -18,3 +18,15 @@ def _torch_threads():
     import torch
     torch.set_num_threads(min(8, os.cpu_count() or 1))
     yield
+
+
+@pytest.fixture(scope="session")
+def pgo():
+    """The product binding with libpgo.so built (built here only if missing
+    or older than its sources)."""
+    from paper_2601_15684_amd import build as B
+    if B.is_stale():
+        B.build()
+    import paper_2601_15684_amd as P
+    P.lib()
+    return P

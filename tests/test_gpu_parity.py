@@ -1,0 +1,266 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU
+oracle on the same seeded inputs.
+
+Tolerances (stated for the sweep in the spec contract): FP64 path
+max-abs 1e-10 on the state after 10 sweeps, FP32 path 1e-4, final cost
+1e-6 relative.  Multipliers are compared as lambda/beta and z/beta: they
+scale with beta and the precisions, while p, q are unitless and t, s are in
+metres.
+"""
+import numpy as np
+import pytest
+import torch
+
+import pgo_synth as S
+from oracle import prep
+from oracle import pradmm as O
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+
+
+def abar(g):
+    n = g.n
+    d = np.zeros(n)
+    np.add.at(d, g.ei, 2 * (g.tau * (g.tm ** 2).sum(1) + g.kappa))
+    np.add.at(d, g.ej, 2 * g.kappa)
+    return float(d.mean())
+
+
+def oracle_run(g, k, beta, gamma=GAMMA):
+    P, p0, t0 = prep.prepare_graph(g)
+    st, prev = O.iterate(P, O.init_state(p0, t0), k, beta, gamma, return_prev=True)
+    return P, st, prev
+
+
+def pack(st):
+    return np.concatenate([st[k].numpy() for k in ("p", "q", "t", "s", "lam", "z")], 1)
+
+
+def scaled_err(a, b, beta):
+    """max-abs per block: p q t s lambda/beta z/beta."""
+    sl = dict(p=slice(0, 4), q=slice(4, 8), t=slice(8, 11), s=slice(11, 14), lam=slice(14, 18),
+              z=slice(18, 21))
+    out = {}
+    for k, s in sl.items():
+        d = np.abs(a[:, s] - b[:, s]).max() if a.shape[0] else 0.0
+        out[k] = d / beta if k in ("lam", "z") else d
+    return out
+
+
+def gpu_run(pgo, g, k, beta, gamma=GAMMA, **opt):
+    with pgo.PoseGraph.from_graph(g, **opt) as h:
+        h.iterate(k, beta, gamma)
+        return h.state(), h.cost()[0], h.residuals()[0]
+
+
+def assert_parity(errs, tol, label=""):
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{label} exceeds {tol}: {bad}"
+
+
+def edge_case_graphs():
+    rng = np.random.default_rng(11)
+    out = []
+    # duplicate and reverse edges, plus an isolated vertex (index 6)
+    g = S.random_small(6, 4, seed=3, sigma_R=0.05, sigma_t=0.05)
+    dup = np.array([0, 1], np.int64)
+    g2 = S._measure(
+        np.concatenate([g.R_gt, S.so3_exp(rng.standard_normal((1, 3)))]),
+        np.concatenate([g.t_gt, rng.standard_normal((1, 3))]),
+        np.concatenate([g.ei, g.ei[dup], g.ej[dup]]), np.concatenate([g.ej, g.ej[dup], g.ei[dup]]),
+        0.05, 0.05, rng, init="gt")
+    g2.R0 = g2.R0 @ S.so3_exp(rng.standard_normal((g2.n, 3)) * 0.1)
+    g2.t0 = g2.t0 + 0.1 * rng.standard_normal((g2.n, 3))
+    out.append(("dup-reverse-isolated", g2))
+    # no edges at all
+    g3 = S.tree(3, seed=1)
+    g3.ei, g3.ej = g3.ei[:0], g3.ej[:0]
+    g3.Rm, g3.tm, g3.kappa, g3.tau = g3.Rm[:0], g3.tm[:0], g3.kappa[:0], g3.tau[:0]
+    out.append(("no-edges", g3))
+    out.append(("single-edge", S.tree(2, seed=2)))
+    # ragged: several tiles plus a tail for every block size tried
+    out.append(("ragged-grid", S.grid(7, 11, 9, p=0.4, sigma_R=0.05, sigma_t=0.1, seed=5)))
+    return out
+
+
+# ---------------------------------------------------------------------------
+def test_prepared_quaternions_match_oracle(pgo):
+    g = S.make_config("grid-1k")
+    P, p0, _ = prep.prepare_graph(g)
+    with pgo.PoseGraph.from_graph(g) as h:
+        qe, pv = h.prepared()
+    assert np.abs(pv - p0.numpy()).max() < 1e-14
+    assert np.abs(qe - P["qm"].numpy()).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", ["circle-100", "grid-1k", "sphere-2.5k"])
+@pytest.mark.parametrize("sched", ["phase", "graph"])
+def test_fp64_state_parity_10_sweeps(pgo, name, sched):
+    g = S.make_config(name)
+    beta = 0.01 * abar(g)
+    _, st, _ = oracle_run(g, 10, beta)
+    got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp64", schedule=sched)
+    assert_parity(scaled_err(got, pack(st), beta), 1e-10, f"{name}/{sched}")
+
+
+@pytest.mark.parametrize("label,g", edge_case_graphs(), ids=lambda x: x if isinstance(x, str) else "")
+def test_fp64_edge_cases(pgo, label, g):
+    beta = 0.05 * max(abar(g), 1.0)
+    _, st, _ = oracle_run(g, 10, beta)
+    for sched in ("phase", "graph"):
+        for block in (64, 256):
+            got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp64", schedule=sched, block=block)
+            assert_parity(scaled_err(got, pack(st), beta), 1e-10, f"{label}/{sched}/{block}")
+
+
+@pytest.mark.parametrize("name", ["circle-100", "grid-1k", "sphere-2.5k"])
+def test_fp32_state_parity_10_sweeps(pgo, name):
+    g = S.make_config(name)
+    beta = 0.01 * abar(g)
+    _, st, _ = oracle_run(g, 10, beta)
+    for sched in ("phase", "graph"):
+        got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp32", schedule=sched)
+        assert_parity(scaled_err(got, pack(st), beta), 1e-4, f"{name}/fp32/{sched}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cost_and_residuals_match_oracle(pgo, prec):
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    P, st, prev = oracle_run(g, 7, beta)
+    ref = np.array(O.residuals(P, prev, st, beta))
+    _, F, res = gpu_run(pgo, g, 7, beta, precision=prec)
+    rtol = 1e-12 if prec == "fp64" else 1e-4
+    assert abs(F - ref[5]) <= rtol * ref[5]
+    assert np.allclose(res, ref, rtol=rtol if prec == "fp64" else 2e-3, atol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_final_cost_500_sweeps(pgo, prec):
+    """grid-1k, 500 sweeps: final cost within 1e-6 relative of the oracle's."""
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    P, st, _ = oracle_run(g, 500, beta)
+    F_ref = float(O.cost(P, st["p"], st["t"]))
+    _, F, _ = gpu_run(pgo, g, 500, beta, precision=prec)
+    assert abs(F - F_ref) <= 1e-6 * F_ref
+
+
+def test_schedules_and_block_sizes_bitwise_identical(pgo):
+    g = S.make_config("sphere-2.5k")
+    beta = 0.01 * abar(g)
+    for prec in ("fp64", "fp32"):
+        ref = None
+        for sched in ("phase", "graph"):
+            for block in (64, 256, 1024):
+                got, _, _ = gpu_run(pgo, g, 6, beta, precision=prec, schedule=sched, block=block)
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got, ref), (prec, sched, block)
+
+
+def test_batched_equals_single_bitwise(pgo):
+    b = S.batched(4096, first=0, count=9)
+    beta = 200.0
+    for prec in ("fp64", "fp32"):
+        with pgo.PoseGraph.from_batch(b, precision=prec) as h:
+            h.iterate(8, beta, GAMMA)
+            allst = h.state()
+            costs = h.cost()
+        voff, _ = b.offsets()
+        for k, gr in enumerate(b.graphs):
+            got, F, _ = gpu_run(pgo, gr, 8, beta, precision=prec)
+            assert np.array_equal(allst[voff[k]:voff[k + 1]], got), (prec, k)
+            assert costs[k] == F
+
+
+def test_batched_parity_with_oracle(pgo):
+    b = S.batched(4096, first=100, count=5)
+    beta = 200.0
+    with pgo.PoseGraph.from_batch(b, precision="fp64") as h:
+        h.iterate(10, beta, GAMMA)
+        allst = h.state()
+    voff, _ = b.offsets()
+    for k, gr in enumerate(b.graphs):
+        _, st, _ = oracle_run(gr, 10, beta)
+        assert_parity(scaled_err(allst[voff[k]:voff[k + 1]], pack(st), beta), 1e-10, gr.name)
+
+
+def test_resume_and_determinism(pgo):
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    for prec in ("fp64", "fp32"):
+        with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+            h.iterate(10, beta, GAMMA)
+            ref = h.state()
+        with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+            h.iterate(4, beta, GAMMA)
+            mid = h.state()
+        with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+            h.set_state(mid)
+            h.iterate(6, beta, GAMMA)
+            assert np.array_equal(h.state(), ref), prec
+
+
+def test_unit_norm_so3_after_every_sweep(pgo):
+    g = S.make_config("sphere-2.5k")
+    beta = 0.01 * abar(g)
+    for prec, tol in (("fp64", 1e-15), ("fp32", 1e-6)):
+        with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+            for _ in range(5):
+                h.iterate(1, beta, GAMMA)
+                p = h.state()[:, 0:4]
+                assert np.abs(np.linalg.norm(p, axis=1) - 1).max() < 4 * tol
+                R, _ = h.poses()
+                assert np.abs(np.transpose(R, (0, 2, 1)) @ R - np.eye(3)).max() < 10 * tol
+                assert np.abs(np.linalg.det(R) - 1).max() < 10 * tol
+
+
+def test_noise_free_fixed_point(pgo):
+    g = S.grid(5, 5, 4, p=0.5, sigma_R=0.0, sigma_t=0.0, init="gt")
+    beta = 0.01 * abar(g)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+            s0 = h.state()
+            h.iterate(5, beta, GAMMA)
+            err = scaled_err(h.state(), s0, beta)
+            assert_parity(err, tol, prec)
+            assert h.cost()[0] < (1e-16 if prec == "fp64" else 1e-6) * g.m * 1e4
+
+
+def test_error_paths(pgo):
+    g = S.make_config("circle-100")
+    with pgo.PoseGraph.from_graph(g) as h:
+        for k, b, gm in ((1, 1.0, 2.0), (1, 1.0, 0.0), (1, 0.0, 1.0), (-1, 1.0, 1.0), (1, np.nan, 1.0)):
+            with pytest.raises(pgo.PgoError) as ex:
+                h.iterate(k, b, gm)
+            assert ex.value.name == "PGO_EINVAL"
+        s0 = h.state()
+        h.iterate(0, 1.0, 1.0)
+        assert np.array_equal(h.state(), s0)
+        bad = s0.copy()
+        bad[3, 9] = np.nan
+        h.set_state(bad)
+        with pytest.raises(pgo.PgoError) as ex:
+            h.cost()
+        assert ex.value.name == "PGO_ENUMERIC"
+    Rm = g.Rm.copy()
+    Rm[5] = -Rm[5]
+    with pytest.raises(pgo.PgoError) as ex:
+        pgo.pgo_create(g.n, g.R0.reshape(-1, 9), g.t0, g.ei, g.ej, Rm.reshape(-1, 9), g.tm, g.kappa,
+                       g.tau)
+    assert ex.value.name == "PGO_EINVAL" and "edge 5" in str(ex.value)
+
+
+def test_full_size_grid_100k_parity(pgo):
+    """The 100k-pose grid at full size in the per-phase schedule, FP32 and
+    FP64, against the oracle after 10 sweeps."""
+    g = S.make_config("grid-100k")
+    beta = 0.01 * abar(g)
+    _, st, _ = oracle_run(g, 10, beta)
+    ref = pack(st)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        got, _, _ = gpu_run(pgo, g, 10, beta, precision=prec, schedule="phase")
+        assert_parity(scaled_err(got, ref, beta), tol, f"grid-100k/{prec}")
