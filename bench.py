@@ -1,25 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the PRADMM sweep on one MI355X.
 
-Workload (headline): 4096 independent SE(3) pose graphs of uneven size
-(poses uniform in [50, 5000], edges/poses uniform in [1.2, 4], circle / grid
-/ sphere topologies, sigma_R ~ U[0.01, 0.1] rad, sigma_t ~ U[0.01, 0.2] m),
-FP32 state, one persistent launch of 50 sweeps per step.  One step is one
-pass of the whole hot path over the batch: 50 sweeps of the four phases
-(p, q, t, s with the multiplier updates) and the FP64 cost/residual
-reductions of every graph.
+Workload (headline, ``batched-4096``): 4096 independent SE(3) pose graphs of
+uneven size (poses uniform in [50, 5000], edges/poses uniform in [1.2, 4],
+circle / grid / sphere topologies, sigma_R ~ U[0.01, 0.1] rad, sigma_t ~
+U[0.01, 0.2] m), FP32 state, one persistent launch of 50 sweeps per step,
+one penalty per graph.  One step is one pass of the whole hot path over the
+batch: 50 sweeps of the four phases (p, q, t, s with the multiplier updates)
+and the FP64 cost/residual reductions of every graph.
 
 Printed: one JSON line with edge-iterations/s (sum over graphs of edges x
 sweeps / wall time of the timed steps), the HBM roofline of the sweep kernel
 (hipEvent-timed launches on the stream the kernel runs on), the plain FP64
-path on the same batch, and the CPU oracle timed on a bounded sample.
+path on the same batch, time to a 1e-6 relative cost gap on the 1000-pose
+grid for both precisions, and the CPU oracle timed on a bounded sample
+(which also checks sampled graphs of the batch against the GPU result).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
 """
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -33,24 +34,24 @@ import pgo_synth as S  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 B_EDGE = 44     # algorithmic bytes per edge per sweep (q~ 16, t~ 12, kappa+tau 8, two indices 8)
-B_VERTEX = 168  # algorithmic bytes per vertex per sweep (21-word FP32 state read and written)
+B_VERTEX = 168  # algorithmic bytes per pose per sweep (21-word FP32 state read and written)
+# bytes one sweep of this layout streams when every phase reads each array it
+# touches once (per edge / per pose), FP32
+B_EDGE_PHASE, B_VERTEX_PHASE = 116, 448
 GAMMA = 1.4
+BETA_SCALE = 0.01
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def beta_for(batch, scale=0.01):
-    """One penalty for the whole batch: scale x the geometric mean over graphs
-    of the mean diagonal weight 2 sum_out (tau |t~|^2 + kappa) + 2 sum_in kappa."""
-    vals = []
-    for g in batch.graphs:
-        d = np.zeros(g.n)
-        np.add.at(d, g.ei, 2 * (g.tau * (g.tm ** 2).sum(1) + g.kappa))
-        np.add.at(d, g.ej, 2 * g.kappa)
-        vals.append(d.mean())
-    return scale * float(np.exp(np.mean(np.log(vals))))
+def abar(g):
+    """Mean over poses of the diagonal weight 2 sum_out (tau |t~|^2 + kappa) + 2 sum_in kappa."""
+    d = np.zeros(g.n)
+    np.add.at(d, g.ei, 2 * (g.tau * (g.tm ** 2).sum(1) + g.kappa))
+    np.add.at(d, g.ej, 2 * g.kappa)
+    return float(d.mean())
 
 
 def source_sha():
@@ -61,9 +62,10 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, per_launch_scale):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when it is missing or was taken on other kernel sources."""
+def load_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/traffic.json), or None when it is missing or was taken on
+    other kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         rec = json.load(open(path))[kernel]
@@ -71,23 +73,34 @@ def load_traffic(kernel, per_launch_scale):
         return None
     if rec.get("source_sha") != source_sha():
         return None
-    kib = rec["fetch_kib_per_dispatch"] + rec["write_kib_per_dispatch"]
-    return kib * 1024.0 * rec.get("copy_factor", 1.0) * per_launch_scale
+    return rec["bytes_per_launch"]
 
 
-def run_gpu(P, torch, batch, voff, eoff, cat, prec, beta, sweeps, steps, warmup, tune=True):
+def copy_calibration(torch, gib=1):
+    """A plain device copy of known size, so that rocprofv3 byte counters can
+    be scaled (FETCH_SIZE/WRITE_SIZE of this copy vs its 2 x size bytes)."""
+    n = gib * (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tune, sched, block):
     stream = torch.cuda.Stream()
-    opt = P.pgo_default_options(precision=prec)
+    opt = P.pgo_default_options(precision=prec, schedule=sched, block=block)
     t0 = time.perf_counter()
     h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
                              cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], cat["tau"], opt)
     create_s = time.perf_counter() - t0
     P.pgo_set_stream(h, stream.cuda_stream)
-    info = P.pgo_autotune(h, beta, GAMMA, sweeps=10) if tune else P.pgo_info(h)
+    info = P.pgo_autotune(h, float(np.median(betas)), GAMMA, sweeps=10) if tune else P.pgo_info(h)
     log(f"[{prec}] created in {create_s:.2f}s, schedule={info['schedule']} block={info['block']}")
     F0 = P.pgo_cost(h)
     for _ in range(warmup):
-        P.pgo_iterate(h, sweeps, beta, GAMMA)
+        P.pgo_iterate_graphs(h, sweeps, betas, GAMMA)
         P.pgo_residuals(h)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
@@ -96,36 +109,90 @@ def run_gpu(P, torch, batch, voff, eoff, cat, prec, beta, sweeps, steps, warmup,
     with torch.cuda.stream(stream):
         for k in range(steps):
             evs[k][0].record(stream)
-            P.pgo_iterate(h, sweeps, beta, GAMMA)
+            P.pgo_iterate_graphs(h, sweeps, betas, GAMMA)
             evs[k][1].record(stream)
             res = P.pgo_residuals(h)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    state = P.pgo_get_state(h)
     P.pgo_destroy(h)
-    return dict(wall=wall, kern_ms=kern_ms, info=info, create_s=create_s, F0=F0, res=res)
+    return dict(wall=wall, kern_ms=kern_ms, info=info, create_s=create_s, F0=F0, res=res,
+                state=state, sweeps_total=(warmup + steps) * sweeps)
 
 
-def cpu_baseline(batch, beta, budget_s=12.0, sweeps=5):
+def time_to_tol(P, g, prec, beta, F_star, tol=1e-6, check_every=10, cap=20000):
+    """Wall time (s) and sweeps until cost <= F*(1 + tol), cost checked every
+    check_every sweeps (the reductions are inside the timed region)."""
+    with P.PoseGraph.from_graph(g, precision=prec) as h:
+        s0 = h.state()
+        h.iterate(check_every, beta, GAMMA)  # first call builds the captured launch sequence
+        h.set_state(s0)
+        t0 = time.perf_counter()
+        done = 0
+        while done < cap:
+            h.iterate(check_every, beta, GAMMA)
+            done += check_every
+            F = h.cost()[0]
+            if F <= F_star * (1 + tol):
+                return time.perf_counter() - t0, done
+        return None, done
+
+
+def converged_cost(P, g, beta, sweeps=40000):
+    with P.PoseGraph.from_graph(g, precision="fp64") as h:
+        best = np.inf
+        for _ in range(sweeps // 1000):
+            h.iterate(1000, beta, GAMMA)
+            best = min(best, h.cost()[0])
+        return best
+
+
+def cpu_leg(batch, betas, voff, gpu32, gpu64, budget_s=12.0, sweeps=5):
+    """The FP64 CPU oracle: (1) timed on a bounded sample of the batch,
+    (2) run on sampled small graphs for as many sweeps as the GPU ran, to
+    state the GPU error per result."""
     import torch
 
     from oracle import prep
     from oracle import pradmm as O
     edges, used, t_total = 0, 0, 0.0
-    for g in batch.graphs:
+    for g, b in zip(batch.graphs, betas):
         Pr, p0, t0 = prep.prepare_graph(g)
         st = O.init_state(p0, t0)
         t = time.perf_counter()
-        O.iterate(Pr, st, sweeps, beta, GAMMA)
+        O.iterate(Pr, st, sweeps, b, GAMMA)
         t_total += time.perf_counter() - t
         edges += g.m * sweeps
         used += 1
         if t_total > budget_s:
             break
-    return dict(value=edges / t_total, unit="edge-iter/s", cores=torch.get_num_threads(),
+    base = dict(value=edges / t_total, unit="edge-iter/s", cores=torch.get_num_threads(),
                 kind="oracle",
                 sample=f"first {used} graphs of the batch, {sweeps} FP64 sweeps each "
-                       f"({edges // sweeps} edges, {t_total:.1f} s of CPU time, sweeps only)")
+                       f"({edges // sweeps} edges, {t_total:.1f} s of sweep time)")
+    # sampled parity: the three smallest graphs of the batch
+    pick = np.argsort([g.n for g in batch.graphs])[:3]
+    errs = {}
+    for prec, run in (("fp32", gpu32), ("fp64", gpu64)):
+        if run is None:
+            continue
+        worst = {}
+        for k in pick:
+            g = batch.graphs[k]
+            Pr, p0, t0 = prep.prepare_graph(g)
+            st = O.iterate(Pr, O.init_state(p0, t0), run["sweeps_total"], betas[k], GAMMA)
+            ref = np.concatenate([st[q].numpy() for q in ("p", "q", "t", "s", "lam", "z")], 1)
+            got = run["state"][voff[k]:voff[k + 1]]
+            for name, sl, sc in (("p", slice(0, 4), 1), ("q", slice(4, 8), 1), ("t", slice(8, 11), 1),
+                                 ("s", slice(11, 14), 1), ("lam/beta", slice(14, 18), betas[k]),
+                                 ("z/beta", slice(18, 21), betas[k])):
+                e = float(np.abs(got[:, sl] - ref[:, sl]).max()) / sc
+                worst[name] = max(worst.get(name, 0.0), e)
+        errs[prec] = worst
+    base["sampled_parity"] = {"graphs": [batch.graphs[k].name for k in pick],
+                              "sweeps": gpu32["sweeps_total"], "max_abs_err": errs}
+    return base
 
 
 def main():
@@ -138,12 +205,17 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-ttt", action="store_true", help="skip the time-to-tolerance leg")
+    ap.add_argument("--no-tune", action="store_true", help="use --schedule/--block as given")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "phase", "graph"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run a 1 GiB device copy first (byte-counter calibration for rocprofv3)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: the batched sweep shards by whole graphs with no "
-              "exchange, so there is no multi-GPU leg in this build (run with --gpus 1).",
-              file=sys.stderr)
+              "exchange, so this build has no multi-GPU leg (run with --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     # inputs first: the generator forks worker processes, which must happen
@@ -153,20 +225,27 @@ def main():
     voff, eoff = batch.offsets()
     cat = batch.concat()
     n, m = int(voff[-1]), int(eoff[-1])
-    beta = beta_for(batch)
-    log(f"generated {args.graphs} graphs: n={n} m={m} in {time.perf_counter() - t0:.1f}s; beta={beta:.4g}")
+    betas = np.array([BETA_SCALE * abar(g) for g in batch.graphs])
+    g1k = S.make_config("grid-1k")
+    beta1k = BETA_SCALE * abar(g1k)
+    log(f"generated {args.graphs} graphs: n={n} m={m} in {time.perf_counter() - t0:.1f}s")
 
     import torch
 
     import paper_2601_15684_amd as P
     P.lib()
     torch.cuda.init()
-    r32 = run_gpu(P, torch, batch, voff, eoff, cat, "fp32", beta, args.sweeps, args.steps, args.warmup)
-    edge_iters = m * args.sweeps * args.steps
-    value = edge_iters / r32["wall"]
+    if args.copy_calib:
+        copy_calibration(torch)
+    tune = not args.no_tune
+    r32 = run_batch(P, torch, cat, voff, eoff, "fp32", betas, args.sweeps, args.steps, args.warmup,
+                    tune, args.schedule, args.block)
+    value = m * args.sweeps * args.steps / r32["wall"]
     algo_bytes = (B_EDGE * m + B_VERTEX * n) * args.sweeps
     achieved = algo_bytes / (r32["kern_ms"] * 1e-3) / 1e9
-    traffic = load_traffic("k_graph_sweeps<float>", 1.0)
+    phase_bytes = (B_EDGE_PHASE * m + B_VERTEX_PHASE * n) * args.sweeps
+    kname = "k_graph_sweeps<float>" if r32["info"]["schedule"] == 2 else "k_phase<*,float>"
+    F0, F1 = r32["F0"], r32["res"][:, 5]
     out = {
         "metric": "edge-iters/s + time to 1e-6 rel cost; FP32/batched vs plain FP64, 1 GPU",
         "value": value,
@@ -181,27 +260,39 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched-4096", "graphs": args.graphs, "poses": n, "edges": m,
-                   "sweeps_per_step": args.sweeps, "beta": beta, "gamma": GAMMA,
-                   "schedule": ["auto", "phase", "graph"][r32["info"]["schedule"]],
+                   "sweeps_per_step": args.sweeps, "beta": f"{BETA_SCALE} x mean diagonal weight, per graph",
+                   "gamma": GAMMA, "schedule": ["auto", "phase", "graph"][r32["info"]["schedule"]],
                    "block": r32["info"]["block"], "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_graph_sweeps<float>" if r32["info"]["schedule"] == 2 else "k_phase<*,float>",
-                     "kernel_ms_per_launch": r32["kern_ms"],
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname),
+                     "kernel": kname, "kernel_ms_per_launch": r32["kern_ms"],
                      "bytes_per_launch": algo_bytes,
-                     "bytes_model": f"{B_EDGE} B/edge + {B_VERTEX} B/pose per sweep"},
-        "final_cost_sum": float(np.sum(r32["res"][:, 5])),
-        "initial_cost_sum": float(np.sum(r32["F0"])),
+                     "bytes_model": f"{B_EDGE} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps",
+                     "phase_model_GBs": phase_bytes / (r32["kern_ms"] * 1e-3) / 1e9},
+        "batch_health": {"graphs_cost_up": int(np.sum(~(F1 <= F0))),
+                         "median_final_over_initial": float(np.median(F1 / F0)),
+                         "worst_final_over_initial": float(np.max(F1 / F0))},
     }
+    r64 = None
     if not args.skip_fp64:
-        r64 = run_gpu(P, torch, batch, voff, eoff, cat, "fp64", beta, args.sweeps,
-                      max(2, args.steps // 2), 1)
-        v64 = m * args.sweeps * max(2, args.steps // 2) / r64["wall"]
+        steps64 = max(2, args.steps // 2)
+        r64 = run_batch(P, torch, cat, voff, eoff, "fp64", betas, args.sweeps, steps64, 1, tune,
+                        args.schedule, args.block)
+        v64 = m * args.sweeps * steps64 / r64["wall"]
         out["fp64"] = {"value": v64, "unit": "edge-iter/s", "kernel_ms_per_launch": r64["kern_ms"],
-                       "speedup_fp32_over_fp64": value / v64,
-                       "final_cost_sum": float(np.sum(r64["res"][:, 5]))}
+                       "speedup_fp32_over_fp64": value / v64}
+    if not args.skip_ttt:
+        F_star = converged_cost(P, g1k, beta1k)
+        ttt = {"workload": "grid-1k", "F_star": F_star,
+               "F_star_from": "min cost of a 40000-sweep FP64 GPU run"}
+        for prec in ("fp64", "fp32"):
+            s, k = time_to_tol(P, g1k, prec, beta1k, F_star)
+            ttt[prec] = {"seconds": s, "sweeps": k}
+        if ttt["fp64"]["seconds"] and ttt["fp32"]["seconds"]:
+            ttt["speedup_fp32_over_fp64"] = ttt["fp64"]["seconds"] / ttt["fp32"]["seconds"]
+        out["time_to_1e-6"] = ttt
     if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(batch, beta)
+        out["cpu_baseline"] = cpu_leg(batch, betas, voff, r32, r64)
     print(json.dumps(out), flush=True)
 
 

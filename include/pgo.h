@@ -109,8 +109,9 @@ pgo_status pgo_create(pgo_graph** out, int32_t n, const double* R0, const double
  * owns poses voff[g]..voff[g+1]-1 and edges eoff[g]..eoff[g+1]-1 of the
  * concatenated arrays (same layouts as pgo_create); ei/ej are graph-local
  * (0 <= ei < voff[g+1]-voff[g]).  voff[0] = eoff[0] = 0, every graph has at
- * least one pose, offsets are nondecreasing.  Sweeps, beta and gamma are
- * shared by all graphs; costs and residuals are reported per graph.
+ * least one pose, offsets are nondecreasing.  Sweeps and gamma are shared
+ * by all graphs; beta is shared (pgo_iterate) or per graph
+ * (pgo_iterate_graphs); costs and residuals are reported per graph.
  */
 pgo_status pgo_create_batched(pgo_graph** out, int32_t G, const int64_t* voff,
                               const int64_t* eoff, const double* R0, const double* t0,
@@ -129,6 +130,15 @@ pgo_status pgo_set_stream(pgo_graph* g, void* hip_stream);
  */
 pgo_status pgo_iterate(pgo_graph* g, int32_t k, double beta, double gamma);
 
+/*
+ * pgo_iterate_graphs -- pgo_iterate with one penalty per graph of the handle:
+ * beta is a host array of G values, each finite and > 0 (graph g runs with
+ * beta[g]; the theory asks beta above a problem-dependent threshold, so a
+ * batch of graphs with very different weight scales needs its own beta per
+ * graph).  The residual e of pgo_residuals then uses each graph's beta.
+ */
+pgo_status pgo_iterate_graphs(pgo_graph* g, int32_t k, const double* beta, double gamma);
+
 /* Cost of model (1) at (p, t), one double per graph, accumulated in FP64. */
 pgo_status pgo_cost(pgo_graph* g, double* F);
 
@@ -137,7 +147,7 @@ pgo_status pgo_cost(pgo_graph* g, double* F);
  *   [0] ||p - q||, [1] ||t - s||,
  *   [2] e = (||dlambda||^2 + ||dz||^2)/beta + beta(||dq||^2 + ||dt||^2)
  *       (iteration residual of App. E.1; d = change over the last sweep,
- *        beta of the last pgo_iterate call; 0 before any sweep),
+ *        the graph's beta of the last iterate call; 0 before any sweep),
  *   [3] beta ||dq||, [4] beta ||ds|| (dual residuals),
  *   [5] cost of model (1).
  * All sums in FP64.  PGO_ENUMERIC if any value is not finite.

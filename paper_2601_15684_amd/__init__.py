@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
-    "pgo_set_stream", "pgo_iterate", "pgo_cost", "pgo_residuals", "pgo_get_poses",
+    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph",
     "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "LIB_PATH",
@@ -55,6 +55,7 @@ _SIGNATURES = {
                                      _D, _D, C.POINTER(PgoOptions)]),
     "pgo_set_stream": (C.c_int, [_P, _P]),
     "pgo_iterate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
+    "pgo_iterate_graphs": (C.c_int, [_P, C.c_int32, _D, C.c_double]),
     "pgo_cost": (C.c_int, [_P, _D]),
     "pgo_residuals": (C.c_int, [_P, _D]),
     "pgo_get_poses": (C.c_int, [_P, _D, _D]),
@@ -158,6 +159,14 @@ def pgo_iterate(h, k, beta, gamma):
     _chk(lib().pgo_iterate(h, int(k), float(beta), float(gamma)))
 
 
+def pgo_iterate_graphs(h, k, beta, gamma):
+    b = _f64(beta)
+    G = pgo_info(h)["G"]
+    if b.shape != (G,):
+        raise ValueError(f"beta must hold one value per graph ({G}), got shape {b.shape}")
+    _chk(lib().pgo_iterate_graphs(h, int(k), _dp(b), float(gamma)))
+
+
 def pgo_info(h):
     n, m = C.c_int64(), C.c_int64()
     G, prec, sched, block = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
@@ -244,7 +253,10 @@ class PoseGraph:
                                       pgo_default_options(**opt)))
 
     def iterate(self, k, beta, gamma):
-        pgo_iterate(self.h, k, beta, gamma)
+        if np.ndim(beta):
+            pgo_iterate_graphs(self.h, k, beta, gamma)
+        else:
+            pgo_iterate(self.h, k, beta, gamma)
 
     def cost(self):
         return pgo_cost(self.h)

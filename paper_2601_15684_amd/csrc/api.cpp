@@ -52,6 +52,9 @@ struct pgo_graph {
   std::vector<int64_t> voff_h, eoff_h;
   int32_t* voff32 = nullptr;
   int32_t* order = nullptr;
+  int32_t* gid = nullptr;           // graph of each vertex
+  double* beta_dev = nullptr;       // per-graph penalties of the last pgo_iterate_graphs
+  std::vector<double> beta_h;       // penalty of each graph in the last iterate call
   int32_t *o_ptr = nullptr, *o_nbr = nullptr, *o_perm = nullptr;
   int32_t *i_ptr = nullptr, *i_nbr = nullptr, *i_perm = nullptr;
   void *o_tt = nullptr, *o_w = nullptr, *i_tt = nullptr, *i_w = nullptr;
@@ -71,12 +74,12 @@ struct pgo_graph {
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
-  double last_beta = 1.0;
   bool have_prev = false;
   // captured launch sequence of the per-phase schedule
   hipGraphExec_t gexec = nullptr;
   int g_k = -1, g_block = -1;
   double g_beta = 0, g_gamma = 0;
+  bool g_per_graph = false;
 };
 
 namespace {
@@ -118,6 +121,7 @@ template <typename T>
 DevGraph<T> view(const pgo_graph* g) {
   DevGraph<T> d;
   d.n = int32_t(g->n);
+  d.gid = g->gid;
   d.o_ptr = g->o_ptr;
   d.o_nbr = g->o_nbr;
   d.o_tt = static_cast<const P4<T>*>(g->o_tt);
@@ -361,6 +365,9 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
     }
   std::vector<int32_t> voff32(static_cast<size_t>(G) + 1);
   for (int32_t k = 0; k <= G; ++k) voff32[size_t(k)] = int32_t(voff[k]);
+  std::vector<int32_t> gidh(static_cast<size_t>(n));
+  for (int32_t k = 0; k < G; ++k)
+    for (int64_t v = voff[k]; v < voff[k + 1]; ++v) gidh[size_t(v)] = k;
   std::vector<int32_t> order(static_cast<size_t>(G));
   std::iota(order.begin(), order.end(), 0);
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
@@ -380,6 +387,9 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   if ((s = upload(g, &Rmd, Rm, size_t(9 * m))) != PGO_OK) return bail(s);
   if ((s = upload(g, &g->voff32, voff32.data(), voff32.size())) != PGO_OK) return bail(s);
   if ((s = upload(g, &g->order, order.data(), order.size())) != PGO_OK) return bail(s);
+  if ((s = upload(g, &g->gid, gidh.data(), gidh.size())) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->beta_dev, size_t(G))) != PGO_OK) return bail(s);
+  g->beta_h.assign(size_t(G), 1.0);
   if ((s = dalloc(g, &g->p0, size_t(n))) != PGO_OK) return bail(s);
   if ((s = dalloc(g, &g->qe, size_t(m))) != PGO_OK) return bail(s);
   if ((s = dalloc(g, &bad, size_t(std::max(n, m)))) != PGO_OK) return bail(s);
@@ -441,8 +451,10 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
 }
 
 template <typename T>
-pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block) {
-  SweepParams sp{beta, gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4};
+pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
+                      bool per_graph) {
+  SweepParams sp{beta, gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4,
+                 per_graph ? g->beta_dev : nullptr};
   const DevGraph<T> d = view<T>(g);
   if (sched == PGO_SCHED_GRAPH) {
     HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->stream));
@@ -453,7 +465,8 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
     HIPCHK(launch_phase_sweeps<T>(d, k, sp, block, g->stream));
     return PGO_OK;
   }
-  if (!(g->gexec && g->g_k == k && g->g_beta == beta && g->g_gamma == gamma && g->g_block == block)) {
+  if (!(g->gexec && g->g_k == k && g->g_beta == beta && g->g_gamma == gamma &&
+        g->g_block == block && g->g_per_graph == per_graph)) {
     if (g->gexec) {
       (void)hipGraphExecDestroy(g->gexec);
       g->gexec = nullptr;
@@ -477,17 +490,28 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
     g->g_beta = beta;
     g->g_gamma = gamma;
     g->g_block = block;
+    g->g_per_graph = per_graph;
   }
   HIPCHK(hipGraphLaunch(g->gexec, g->stream));
   return PGO_OK;
 }
 
-pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block) {
-  pgo_status s = g->opt.precision == PGO_FP64 ? run_sweeps<double>(g, k, beta, gamma, sched, block)
-                                              : run_sweeps<float>(g, k, beta, gamma, sched, block);
+pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
+                        const double* beta_g = nullptr) {
+  const bool per_graph = beta_g != nullptr;
+  if (per_graph)
+    HIPCHK(hipMemcpyAsync(g->beta_dev, beta_g, sizeof(double) * g->G, hipMemcpyHostToDevice,
+                          g->stream));
+  pgo_status s =
+      g->opt.precision == PGO_FP64
+          ? run_sweeps<double>(g, k, beta, gamma, sched, block, per_graph)
+          : run_sweeps<float>(g, k, beta, gamma, sched, block, per_graph);
   if (s == PGO_OK) {
     g->have_prev = true;
-    g->last_beta = beta;
+    if (per_graph)
+      g->beta_h.assign(beta_g, beta_g + g->G);
+    else
+      g->beta_h.assign(size_t(g->G), beta);
   }
   return s;
 }
@@ -571,6 +595,19 @@ pgo_status pgo_iterate(pgo_graph* g, int32_t k, double beta, double gamma) {
   return iterate_with(g, k, beta, gamma, g->sched, block);
 }
 
+pgo_status pgo_iterate_graphs(pgo_graph* g, int32_t k, const double* beta, double gamma) {
+  if (!g || !beta) return fail(PGO_EINVAL, "NULL argument");
+  if (k < 0) return fail(PGO_EINVAL, "k must be >= 0");
+  for (int32_t j = 0; j < g->G; ++j)
+    if (!(std::isfinite(beta[j]) && beta[j] > 0.0))
+      return fail(PGO_EINVAL, "beta of graph " + std::to_string(j) + " must be finite and > 0");
+  if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
+  if (k == 0) return PGO_OK;
+  HIPCHK(hipSetDevice(g->device));
+  const int block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
+  return iterate_with(g, k, beta[0], gamma, g->sched, block, beta);
+}
+
 pgo_status pgo_cost(pgo_graph* g, double* F) {
   if (!g || !F) return fail(PGO_EINVAL, "NULL argument");
   std::vector<double> r;
@@ -585,8 +622,8 @@ pgo_status pgo_residuals(pgo_graph* g, double* out) {
   std::vector<double> r;
   pgo_status s = reduce(g, r);
   if (s != PGO_OK) return s;
-  const double b = g->last_beta;
   for (int32_t k = 0; k < g->G; ++k) {
+    const double b = g->beta_h[size_t(k)];
     const double* v = &r[size_t(kRedVals) * k];
     double* o = out + 6 * size_t(k);
     o[0] = std::sqrt(v[1]);

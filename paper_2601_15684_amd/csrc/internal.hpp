@@ -24,6 +24,7 @@ namespace pgo {
 template <typename T>
 struct DevGraph {
   int32_t n;
+  const int32_t* gid;  // graph of each vertex (per-graph penalties)
   const int32_t* o_ptr;
   const int32_t* o_nbr;
   const P4<T>* o_tt;
@@ -51,6 +52,7 @@ struct DevGraph {
 
 struct SweepParams {
   double beta, gamma, h1, h2, h3, h4;
+  const double* beta_g;  // per-graph penalties (device, G values) or nullptr
 };
 
 // Launchers (sweep.hip).  Every launcher checks its own configuration and

@@ -208,6 +208,7 @@ template <int PH, typename T>
 __global__ void k_phase(DevGraph<T> g, SweepParams sp, int save) {
   const int i = xcd_block() * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
+  if (sp.beta_g) sp.beta = sp.beta_g[g.gid[i]];
   if (PH == 0) vertex_P(g, i, sp);
   if (PH == 1) vertex_Q(g, i, sp, save != 0);
   if (PH == 2) vertex_T(g, i, sp, save != 0);
@@ -243,6 +244,7 @@ __global__ void k_graph_sweeps(DevGraph<T> g, const int32_t* __restrict__ voff,
                                const int32_t* __restrict__ order, int k, SweepParams sp) {
   const int gr = order[blockIdx.x];
   const int v0 = voff[gr], v1 = voff[gr + 1];
+  if (sp.beta_g) sp.beta = sp.beta_g[gr];
   for (int it = 0; it < k; ++it) {
     const bool save = it == k - 1;
     for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_P(g, i, sp);
