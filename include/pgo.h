@@ -154,6 +154,39 @@ pgo_status pgo_cost(pgo_graph* g, double* F);
  */
 pgo_status pgo_residuals(pgo_graph* g, double* out);
 
+/*
+ * Merit values, 2 doubles per graph: [0] the augmented Lagrangian L_beta
+ * (PRADMM section, beta1 = beta2 = the graph's beta) at the current state,
+ * [1] Psi = L_beta + alpha1/(gamma beta) ||dlambda||^2, alpha1 =
+ * |1-gamma|/(1-|1-gamma|): the Lyapunov function of Theorem 1 without its
+ * proximal-difference terms (whose weights the paper leaves implicit).
+ * Uses the beta and gamma of the last iterate/solve call.  FP64 sums.
+ */
+pgo_status pgo_merit(pgo_graph* g, double* out);
+
+/*
+ * pgo_solve -- the outer loop of Alg. 1 with the experiments' stopping rule
+ * and penalty check, per graph.  Sweeps run in chunks of check_every (one
+ * launch per chunk for all graphs still running).  After each chunk, for
+ * every running graph:
+ *   - if beta_growth > 1 and its merit Psi (see pgo_merit) rose over the
+ *     chunk, the chunk is undone for that graph (state restored on the
+ *     device) and its beta multiplied by beta_growth (at most 40 times per
+ *     call; Theorem 1 asks beta above a threshold the paper does not give,
+ *     and the experiments adjust beta by checking exactly this descent);
+ *   - otherwise the chunk is accepted; the graph stops when its residual
+ *     e (App. E.1) is below tol (tol <= 0: never) or after max_sweeps
+ *     accepted sweeps.
+ *   max_sweeps  accepted sweeps per graph, a multiple of check_every
+ *   beta        in/out, G values > 0 (the penalties reached)
+ *   sweeps_done out, G values (accepted sweeps), may be NULL
+ *   converged   out, G values (1 where e < tol stopped the graph), may be NULL
+ * Synchronises the stream once per chunk.
+ */
+pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, double gamma,
+                     double tol, double beta_growth, double* beta, int32_t* sweeps_done,
+                     int32_t* converged);
+
 /* Current poses: R(p_i) (n x 9, row-major) and t_i (n x 3); either may be NULL. */
 pgo_status pgo_get_poses(pgo_graph* g, double* R, double* t);
 

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
-    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_residuals", "pgo_get_poses",
+    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph",
     "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "LIB_PATH",
@@ -57,6 +57,9 @@ _SIGNATURES = {
     "pgo_iterate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
     "pgo_iterate_graphs": (C.c_int, [_P, C.c_int32, _D, C.c_double]),
     "pgo_cost": (C.c_int, [_P, _D]),
+    "pgo_merit": (C.c_int, [_P, _D]),
+    "pgo_solve": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, _D, _I32,
+                            _I32]),
     "pgo_residuals": (C.c_int, [_P, _D]),
     "pgo_get_poses": (C.c_int, [_P, _D, _D]),
     "pgo_get_state": (C.c_int, [_P, _D]),
@@ -182,6 +185,23 @@ def pgo_cost(h):
     return out
 
 
+def pgo_merit(h):
+    out = np.empty((pgo_info(h)["G"], 2), np.float64)
+    _chk(lib().pgo_merit(h, _dp(out)))
+    return out
+
+
+def pgo_solve(h, max_sweeps, check_every, gamma, tol, beta_growth, beta):
+    """Returns (beta reached, accepted sweeps, converged flags), one per graph."""
+    G = pgo_info(h)["G"]
+    b = np.array(np.broadcast_to(np.asarray(beta, np.float64), (G,)))
+    done = np.zeros(G, np.int32)
+    conv = np.zeros(G, np.int32)
+    _chk(lib().pgo_solve(h, int(max_sweeps), int(check_every), float(gamma), float(tol),
+                         float(beta_growth), _dp(b), _ip(done), _ip(conv)))
+    return b, done, conv.astype(bool)
+
+
 def pgo_residuals(h):
     out = np.empty((pgo_info(h)["G"], 6), np.float64)
     _chk(lib().pgo_residuals(h, _dp(out)))
@@ -263,6 +283,12 @@ class PoseGraph:
 
     def residuals(self):
         return pgo_residuals(self.h)
+
+    def merit(self):
+        return pgo_merit(self.h)
+
+    def solve(self, max_sweeps, check_every, gamma, beta, tol=0.0, beta_growth=2.0):
+        return pgo_solve(self.h, max_sweeps, check_every, gamma, tol, beta_growth, beta)
 
     def poses(self):
         return pgo_get_poses(self.h)

@@ -55,6 +55,10 @@ struct pgo_graph {
   int32_t* gid = nullptr;           // graph of each vertex
   double* beta_dev = nullptr;       // per-graph penalties of the last pgo_iterate_graphs
   std::vector<double> beta_h;       // penalty of each graph in the last iterate call
+  double last_gamma = 1.0;
+  int32_t* active_dev = nullptr;    // per-graph run flags (pgo_solve)
+  int32_t* flag_dev = nullptr;      // per-graph restore flags (pgo_solve)
+  void* snap[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   int32_t *o_ptr = nullptr, *o_nbr = nullptr, *o_perm = nullptr;
   int32_t *i_ptr = nullptr, *i_nbr = nullptr, *i_perm = nullptr;
   void *o_tt = nullptr, *o_w = nullptr, *i_tt = nullptr, *i_w = nullptr;
@@ -80,6 +84,7 @@ struct pgo_graph {
   int g_k = -1, g_block = -1;
   double g_beta = 0, g_gamma = 0;
   bool g_per_graph = false;
+  bool g_masked = false;
 };
 
 namespace {
@@ -227,8 +232,8 @@ pgo_status build_chunks(pgo_graph* g) {
   if ((s = upload(g, &g->vc_end, ve.data(), ve.size())) != PGO_OK) return s;
   if ((s = upload(g, &g->g_ec_off, goe.data(), goe.size())) != PGO_OK) return s;
   if ((s = upload(g, &g->g_vc_off, gov.data(), gov.size())) != PGO_OK) return s;
-  if ((s = dalloc(g, &g->part_e, size_t(std::max(1, g->n_ech)))) != PGO_OK) return s;
-  if ((s = dalloc(g, &g->part_v, size_t(7) * std::max(1, g->n_vch))) != PGO_OK) return s;
+  if ((s = dalloc(g, &g->part_e, size_t(kEdgeVals) * std::max(1, g->n_ech))) != PGO_OK) return s;
+  if ((s = dalloc(g, &g->part_v, size_t(kVertVals) * std::max(1, g->n_vch))) != PGO_OK) return s;
   if ((s = dalloc(g, &g->red_out, size_t(kRedVals) * g->G)) != PGO_OK) return s;
   return PGO_OK;
 }
@@ -389,6 +394,8 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   if ((s = upload(g, &g->order, order.data(), order.size())) != PGO_OK) return bail(s);
   if ((s = upload(g, &g->gid, gidh.data(), gidh.size())) != PGO_OK) return bail(s);
   if ((s = dalloc(g, &g->beta_dev, size_t(G))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->active_dev, size_t(G))) != PGO_OK) return bail(s);
+  if ((s = dalloc(g, &g->flag_dev, size_t(G))) != PGO_OK) return bail(s);
   g->beta_h.assign(size_t(G), 1.0);
   if ((s = dalloc(g, &g->p0, size_t(n))) != PGO_OK) return bail(s);
   if ((s = dalloc(g, &g->qe, size_t(m))) != PGO_OK) return bail(s);
@@ -452,9 +459,9 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
 
 template <typename T>
 pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
-                      bool per_graph) {
+                      bool per_graph, bool masked) {
   SweepParams sp{beta, gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4,
-                 per_graph ? g->beta_dev : nullptr};
+                 per_graph ? g->beta_dev : nullptr, masked ? g->active_dev : nullptr};
   const DevGraph<T> d = view<T>(g);
   if (sched == PGO_SCHED_GRAPH) {
     HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->stream));
@@ -466,7 +473,7 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
     return PGO_OK;
   }
   if (!(g->gexec && g->g_k == k && g->g_beta == beta && g->g_gamma == gamma &&
-        g->g_block == block && g->g_per_graph == per_graph)) {
+        g->g_block == block && g->g_per_graph == per_graph && g->g_masked == masked)) {
     if (g->gexec) {
       (void)hipGraphExecDestroy(g->gexec);
       g->gexec = nullptr;
@@ -491,23 +498,29 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
     g->g_gamma = gamma;
     g->g_block = block;
     g->g_per_graph = per_graph;
+    g->g_masked = masked;
   }
   HIPCHK(hipGraphLaunch(g->gexec, g->stream));
   return PGO_OK;
 }
 
 pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
-                        const double* beta_g = nullptr) {
+                        const double* beta_g = nullptr, const int32_t* active = nullptr) {
   const bool per_graph = beta_g != nullptr;
+  const bool masked = active != nullptr;
   if (per_graph)
     HIPCHK(hipMemcpyAsync(g->beta_dev, beta_g, sizeof(double) * g->G, hipMemcpyHostToDevice,
                           g->stream));
+  if (masked)
+    HIPCHK(hipMemcpyAsync(g->active_dev, active, sizeof(int32_t) * g->G, hipMemcpyHostToDevice,
+                          g->stream));
   pgo_status s =
       g->opt.precision == PGO_FP64
-          ? run_sweeps<double>(g, k, beta, gamma, sched, block, per_graph)
-          : run_sweeps<float>(g, k, beta, gamma, sched, block, per_graph);
+          ? run_sweeps<double>(g, k, beta, gamma, sched, block, per_graph, masked)
+          : run_sweeps<float>(g, k, beta, gamma, sched, block, per_graph, masked);
   if (s == PGO_OK) {
     g->have_prev = true;
+    g->last_gamma = gamma;
     if (per_graph)
       g->beta_h.assign(beta_g, beta_g + g->G);
     else
@@ -541,6 +554,55 @@ pgo_status reduce(pgo_graph* g, std::vector<double>& out) {
 pgo_status ensure_iobuf(pgo_graph* g) {
   if (g->iobuf) return PGO_OK;
   return dalloc(g, &g->iobuf, size_t(21) * g->n);
+}
+
+}  // namespace
+
+namespace {
+
+// L_beta (PRADMM section) and the merit of Theorem 1 without its unknown
+// proximal-difference terms, from one graph's reduction values.
+void merit_of(const double* v, double beta, double gamma, double* L, double* psi) {
+  const double a1 = std::fabs(1.0 - gamma) / (1.0 - std::fabs(1.0 - gamma));
+  *L = v[kSplit] - v[kLamPQ] + 0.5 * beta * v[kPQ2] - v[kZTS] + 0.5 * beta * v[kTS2];
+  *psi = *L + a1 / (gamma * beta) * v[kDL2];
+}
+
+template <typename T>
+pgo_status snapshot_or_restore(pgo_graph* g, bool restore) {
+  const size_t n = size_t(g->n);
+  const size_t bytes = 4 * sizeof(T) * n;
+  void* cur[6] = {g->p, g->q, g->lam, g->t, g->s, g->z};
+  if (!restore) {
+    for (int k = 0; k < 6; ++k) {
+      if (!g->snap[k]) {
+        pgo_status s = dalloc_bytes(g, &g->snap[k], bytes);
+        if (s != PGO_OK) return s;
+      }
+      HIPCHK(hipMemcpyAsync(g->snap[k], cur[k], bytes, hipMemcpyDeviceToDevice, g->stream));
+    }
+    return PGO_OK;
+  }
+  HIPCHK(launch_restore<T>(view<T>(g), static_cast<const Q4<T>*>(g->snap[0]),
+                           static_cast<const Q4<T>*>(g->snap[1]), static_cast<const Q4<T>*>(g->snap[2]),
+                           static_cast<const P4<T>*>(g->snap[3]), static_cast<const P4<T>*>(g->snap[4]),
+                           static_cast<const P4<T>*>(g->snap[5]), g->flag_dev, g->stream));
+  return PGO_OK;
+}
+
+pgo_status snapshot(pgo_graph* g) {
+  return g->opt.precision == PGO_FP64 ? snapshot_or_restore<double>(g, false)
+                                      : snapshot_or_restore<float>(g, false);
+}
+
+pgo_status restore_flagged(pgo_graph* g, const std::vector<int32_t>& flags) {
+  HIPCHK(hipMemcpyAsync(g->flag_dev, flags.data(), sizeof(int32_t) * g->G, hipMemcpyHostToDevice,
+                        g->stream));
+  pgo_status s = g->opt.precision == PGO_FP64 ? snapshot_or_restore<double>(g, true)
+                                              : snapshot_or_restore<float>(g, true);
+  if (s != PGO_OK) return s;
+  HIPCHK(hipStreamSynchronize(g->stream));  // flags live on the host stack
+  return PGO_OK;
 }
 
 }  // namespace
@@ -608,12 +670,94 @@ pgo_status pgo_iterate_graphs(pgo_graph* g, int32_t k, const double* beta, doubl
   return iterate_with(g, k, beta[0], gamma, g->sched, block, beta);
 }
 
+pgo_status pgo_merit(pgo_graph* g, double* out) {
+  if (!g || !out) return fail(PGO_EINVAL, "NULL argument");
+  std::vector<double> r;
+  pgo_status s = reduce(g, r);
+  if (s != PGO_OK) return s;
+  for (int32_t k = 0; k < g->G; ++k)
+    merit_of(&r[size_t(kRedVals) * k], g->beta_h[size_t(k)], g->last_gamma, &out[2 * size_t(k)],
+             &out[2 * size_t(k) + 1]);
+  return PGO_OK;
+}
+
+pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, double gamma,
+                     double tol, double beta_growth, double* beta, int32_t* sweeps_done,
+                     int32_t* converged) {
+  if (!g || !beta) return fail(PGO_EINVAL, "NULL argument");
+  if (check_every < 1 || max_sweeps < 0 || max_sweeps % check_every != 0)
+    return fail(PGO_EINVAL, "need check_every >= 1 and max_sweeps a multiple of check_every");
+  if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
+  if (!(beta_growth >= 1.0) || !std::isfinite(beta_growth) || !std::isfinite(tol))
+    return fail(PGO_EINVAL, "beta_growth must be >= 1 and tol finite");
+  const int32_t G = g->G;
+  for (int32_t j = 0; j < G; ++j)
+    if (!(std::isfinite(beta[j]) && beta[j] > 0.0))
+      return fail(PGO_EINVAL, "beta of graph " + std::to_string(j) + " must be finite and > 0");
+  HIPCHK(hipSetDevice(g->device));
+  const bool adapt = beta_growth > 1.0;
+  constexpr int kMaxRejects = 40;
+  std::vector<int32_t> active(size_t(G), 1), done(size_t(G), 0), conv(size_t(G), 0),
+      rejects(size_t(G), 0), flags(size_t(G), 0);
+  std::vector<double> r, r_acc;
+  pgo_status s = reduce(g, r_acc);  // values at the start: the accepted reference
+  if (s != PGO_OK) return s;
+  const int block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
+  g->last_gamma = gamma;
+  for (;;) {
+    bool any = false;
+    for (int32_t j = 0; j < G; ++j) {
+      if (done[size_t(j)] >= max_sweeps) active[size_t(j)] = 0;
+      any = any || active[size_t(j)];
+    }
+    if (!any) break;
+    if (adapt && (s = snapshot(g)) != PGO_OK) return s;
+    if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta, active.data())) !=
+        PGO_OK)
+      return s;
+    if ((s = reduce(g, r)) != PGO_OK) return s;
+    bool any_restore = false;
+    for (int32_t j = 0; j < G; ++j) {
+      flags[size_t(j)] = 0;
+      if (!active[size_t(j)]) {
+        std::copy(&r[size_t(kRedVals) * j], &r[size_t(kRedVals) * (j + 1)],
+                  &r_acc[size_t(kRedVals) * j]);
+        continue;
+      }
+      const double* v = &r[size_t(kRedVals) * j];
+      double L1, psi1, L0, psi0;
+      merit_of(v, beta[j], gamma, &L1, &psi1);
+      merit_of(&r_acc[size_t(kRedVals) * j], beta[j], gamma, &L0, &psi0);
+      if (adapt && psi1 > psi0 + 1e-12 * std::fabs(psi0) && rejects[size_t(j)] < kMaxRejects) {
+        flags[size_t(j)] = 1;  // undo this graph's chunk and raise its penalty
+        any_restore = true;
+        beta[j] *= beta_growth;
+        ++rejects[size_t(j)];
+        continue;
+      }
+      std::copy(v, v + kRedVals, &r_acc[size_t(kRedVals) * j]);
+      done[size_t(j)] += check_every;
+      const double b = beta[j];
+      const double e = (v[kDL2] + v[kDZ2]) / b + b * (v[kDQ2] + v[kDT2]);
+      if (tol > 0.0 && e < tol) {
+        conv[size_t(j)] = 1;
+        active[size_t(j)] = 0;
+      }
+    }
+    if (any_restore && (s = restore_flagged(g, flags)) != PGO_OK) return s;
+  }
+  g->beta_h.assign(beta, beta + G);
+  if (sweeps_done) std::copy(done.begin(), done.end(), sweeps_done);
+  if (converged) std::copy(conv.begin(), conv.end(), converged);
+  return PGO_OK;
+}
+
 pgo_status pgo_cost(pgo_graph* g, double* F) {
   if (!g || !F) return fail(PGO_EINVAL, "NULL argument");
   std::vector<double> r;
   pgo_status s = reduce(g, r);
   if (s != PGO_OK) return s;
-  for (int32_t k = 0; k < g->G; ++k) F[k] = r[size_t(kRedVals) * k];
+  for (int32_t k = 0; k < g->G; ++k) F[k] = r[size_t(kRedVals) * k + kCost];
   return PGO_OK;
 }
 
@@ -626,12 +770,12 @@ pgo_status pgo_residuals(pgo_graph* g, double* out) {
     const double b = g->beta_h[size_t(k)];
     const double* v = &r[size_t(kRedVals) * k];
     double* o = out + 6 * size_t(k);
-    o[0] = std::sqrt(v[1]);
-    o[1] = std::sqrt(v[2]);
-    o[2] = (v[3] + v[4]) / b + b * (v[5] + v[6]);
-    o[3] = b * std::sqrt(v[5]);
-    o[4] = b * std::sqrt(v[7]);
-    o[5] = v[0];
+    o[0] = std::sqrt(v[kPQ2]);
+    o[1] = std::sqrt(v[kTS2]);
+    o[2] = (v[kDL2] + v[kDZ2]) / b + b * (v[kDQ2] + v[kDT2]);
+    o[3] = b * std::sqrt(v[kDQ2]);
+    o[4] = b * std::sqrt(v[kDS2]);
+    o[5] = v[kCost];
   }
   return PGO_OK;
 }

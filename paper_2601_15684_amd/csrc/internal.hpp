@@ -52,7 +52,8 @@ struct DevGraph {
 
 struct SweepParams {
   double beta, gamma, h1, h2, h3, h4;
-  const double* beta_g;  // per-graph penalties (device, G values) or nullptr
+  const double* beta_g;   // per-graph penalties (device, G values) or nullptr
+  const int32_t* active;  // per-graph run flags (device, G values) or nullptr = all run
 };
 
 // Launchers (sweep.hip).  Every launcher checks its own configuration and
@@ -63,6 +64,13 @@ hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& s
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
                                int G, int k, const SweepParams& sp, int block, hipStream_t st);
+
+// Per-graph snapshot restore: every vertex of a graph with flag[g] != 0 gets
+// its state (p, q, lambda, t, s, z) back from the snapshot arrays.
+template <typename T>
+hipError_t launch_restore(const DevGraph<T>& g, const Q4<T>* p, const Q4<T>* q, const Q4<T>* lam,
+                          const P4<T>* t, const P4<T>* s, const P4<T>* z, const int32_t* flag,
+                          hipStream_t st);
 
 // Boundary preparation (prep.hip), FP64.
 // bad[i] = 1 where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
@@ -105,7 +113,23 @@ struct EdgeF64 {  // caller-order FP64 copy of the prepared edges for the cost
   const double* kappa;
   const double* tau;
 };
-constexpr int kRedVals = 8;  // cost, |p-q|^2, |t-s|^2, |dl|^2, |dz|^2, |dq|^2, |dt|^2, |ds|^2
+// Per-graph reduction output, kRedVals doubles per graph:
+enum RedIdx {
+  kCost = 0,   // model (1) at (p, t)
+  kSplit,      // f + g of eq. 2
+  kPQ2,        // |p - q|^2
+  kTS2,        // |t - s|^2
+  kDL2,        // |lambda - lambda_prev|^2
+  kDZ2,        // |z - z_prev|^2
+  kDQ2,        // |q - q_prev|^2
+  kDT2,        // |t - t_prev|^2
+  kDS2,        // |s - s_prev|^2
+  kLamPQ,      // <lambda, p - q>
+  kZTS,        // <z, t - s>
+  kRedVals
+};
+constexpr int kEdgeVals = 2;  // kCost, kSplit
+constexpr int kVertVals = 9;  // kPQ2 .. kZTS
 template <typename T>
 hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
                          const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,

@@ -10,7 +10,6 @@ namespace pgo {
 namespace {
 
 constexpr int kRB = 256;
-constexpr int kVVals = 7;  // |p-q|^2 |t-s|^2 |dl|^2 |dz|^2 |dq|^2 |dt|^2 |ds|^2
 
 template <int K>
 __device__ void block_sum(double (&v)[K], double (*sh)[kRB]) {
@@ -42,17 +41,40 @@ __device__ double edge_cost(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
          E.kappa[e] * (a0 * a0 + a.x * a.x + a.y * a.y + a.z * a.z);
 }
 
+// f + g of the split model (eq. 2) for edge e = (i -> j):
+// tau |[0, t_j - s_i] - q_i [0, t~] p_i^*|^2 + kappa |p_j^* q_i q~ - 1|^2
+template <typename T>
+__device__ double edge_split(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
+  const int i = E.ei[e], j = E.ej[e];
+  const Q4<double> pi = cvt<double>(g.p[i]), qi = cvt<double>(g.q[i]), pj = cvt<double>(g.p[j]);
+  const P4<T> si = g.s[i], tj = g.t[j];
+  const V3<double> tt = {E.tm[3 * e], E.tm[3 * e + 1], E.tm[3 * e + 2]};
+  const Q4<double> rot = qmul(qmul_vp(qi, tt), qconj(pi));  // q_i [0, t~] p_i^*
+  const double r0 = -rot.w;
+  const double r1 = (double(tj.x) - double(si.x)) - rot.x;
+  const double r2 = (double(tj.y) - double(si.y)) - rot.y;
+  const double r3 = (double(tj.z) - double(si.z)) - rot.z;
+  const Q4<double> a = qmul(qmul(qconj(pj), qi), E.q[e]);
+  const double a0 = a.w - 1.0;
+  return E.tau[e] * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3) +
+         E.kappa[e] * (a0 * a0 + a.x * a.x + a.y * a.y + a.z * a.z);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kRB) k_red_edges(DevGraph<T> g, EdgeF64 E,
                                                     const int64_t* __restrict__ beg,
                                                     const int64_t* __restrict__ end,
                                                     double* __restrict__ partial) {
-  __shared__ double sh[1][kRB];
-  double v[1] = {0.0};
+  __shared__ double sh[kEdgeVals][kRB];
+  double v[kEdgeVals] = {0.0, 0.0};
   const int c = blockIdx.x;
-  for (int64_t e = beg[c] + threadIdx.x; e < end[c]; e += kRB) v[0] += edge_cost(g, E, e);
-  block_sum<1>(v, sh);
-  if (threadIdx.x == 0) partial[c] = v[0];
+  for (int64_t e = beg[c] + threadIdx.x; e < end[c]; e += kRB) {
+    v[0] += edge_cost(g, E, e);
+    v[1] += edge_split(g, E, e);
+  }
+  block_sum<kEdgeVals>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kEdgeVals; ++k) partial[kEdgeVals * int64_t(c) + k] = v[k];
 }
 
 template <typename T, typename V>
@@ -68,17 +90,32 @@ __device__ __forceinline__ double d2q(const Q4<T>& a, const Q4<T>& b) {
   return w * w + d2<T, Q4<T>>(a, b);
 }
 
+// <l, a - b> for 4-vectors and 3-vectors
+template <typename T>
+__device__ __forceinline__ double dotq(const Q4<T>& l, const Q4<T>& a, const Q4<T>& b) {
+  return double(l.w) * (double(a.w) - double(b.w)) + double(l.x) * (double(a.x) - double(b.x)) +
+         double(l.y) * (double(a.y) - double(b.y)) + double(l.z) * (double(a.z) - double(b.z));
+}
+
+template <typename T>
+__device__ __forceinline__ double dot3(const P4<T>& l, const P4<T>& a, const P4<T>& b) {
+  return double(l.x) * (double(a.x) - double(b.x)) + double(l.y) * (double(a.y) - double(b.y)) +
+         double(l.z) * (double(a.z) - double(b.z));
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kRB) k_red_vertices(DevGraph<T> g, int have_prev,
                                                        const int64_t* __restrict__ beg,
                                                        const int64_t* __restrict__ end,
                                                        double* __restrict__ partial) {
-  __shared__ double sh[kVVals][kRB];
-  double v[kVVals] = {0, 0, 0, 0, 0, 0, 0};
+  __shared__ double sh[kVertVals][kRB];
+  double v[kVertVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int c = blockIdx.x;
   for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
     v[0] += d2q(g.p[i], g.q[i]);
     v[1] += d2<T, P4<T>>(g.t[i], g.s[i]);
+    v[7] += dotq(g.lam[i], g.p[i], g.q[i]);
+    v[8] += dot3(g.z[i], g.t[i], g.s[i]);
     if (have_prev) {
       v[2] += d2q(g.lam[i], g.lam_prev[i]);
       v[3] += d2<T, P4<T>>(g.z[i], g.z_prev[i]);
@@ -87,9 +124,9 @@ __global__ void __launch_bounds__(kRB) k_red_vertices(DevGraph<T> g, int have_pr
       v[6] += d2<T, P4<T>>(g.s[i], g.s_prev[i]);
     }
   }
-  block_sum<kVVals>(v, sh);
+  block_sum<kVertVals>(v, sh);
   if (threadIdx.x == 0)
-    for (int k = 0; k < kVVals; ++k) partial[kVVals * int64_t(c) + k] = v[k];
+    for (int k = 0; k < kVertVals; ++k) partial[kVertVals * int64_t(c) + k] = v[k];
 }
 
 __global__ void k_red_finish(const double* __restrict__ pe, const double* __restrict__ pv,
@@ -97,13 +134,14 @@ __global__ void k_red_finish(const double* __restrict__ pe, const double* __rest
                              const int32_t* __restrict__ g_vc_off, int G, double* __restrict__ out) {
   const int gr = blockIdx.x * blockDim.x + threadIdx.x;
   if (gr >= G) return;
-  double c = 0.0;
-  for (int k = g_ec_off[gr]; k < g_ec_off[gr + 1]; ++k) c += pe[k];
-  double v[kVVals] = {0, 0, 0, 0, 0, 0, 0};
+  double c[kEdgeVals] = {0.0, 0.0};
+  for (int k = g_ec_off[gr]; k < g_ec_off[gr + 1]; ++k)
+    for (int q = 0; q < kEdgeVals; ++q) c[q] += pe[kEdgeVals * int64_t(k) + q];
+  double v[kVertVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = g_vc_off[gr]; k < g_vc_off[gr + 1]; ++k)
-    for (int q = 0; q < kVVals; ++q) v[q] += pv[kVVals * int64_t(k) + q];
-  out[kRedVals * int64_t(gr)] = c;
-  for (int q = 0; q < kVVals; ++q) out[kRedVals * int64_t(gr) + 1 + q] = v[q];
+    for (int q = 0; q < kVertVals; ++q) v[q] += pv[kVertVals * int64_t(k) + q];
+  for (int q = 0; q < kEdgeVals; ++q) out[kRedVals * int64_t(gr) + q] = c[q];
+  for (int q = 0; q < kVertVals; ++q) out[kRedVals * int64_t(gr) + kEdgeVals + q] = v[q];
 }
 
 }  // namespace

@@ -1,0 +1,105 @@
+"""GPU tests of the outer loop: merit values against the oracle, the
+per-graph stopping rule (App. E.1) and the penalty check (descent of the
+merit of Theorem 1, as the experiments section describes)."""
+import numpy as np
+import pytest
+
+import pgo_synth as S
+from oracle import prep
+from oracle import pradmm as O
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+
+
+def abar(g):
+    d = np.zeros(g.n)
+    np.add.at(d, g.ei, 2 * (g.tau * (g.tm ** 2).sum(1) + g.kappa))
+    np.add.at(d, g.ej, 2 * g.kappa)
+    return float(d.mean())
+
+
+@pytest.mark.parametrize("prec,rtol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_merit_matches_oracle(pgo, prec, rtol):
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    P, p0, t0 = prep.prepare_graph(g)
+    st, prev = O.iterate(P, O.init_state(p0, t0), 7, beta, GAMMA, return_prev=True)
+    L = float(O.aug_lagrangian(P, st, beta))
+    a1 = abs(1 - GAMMA) / (1 - abs(1 - GAMMA))
+    psi = L + a1 / (GAMMA * beta) * float(((st["lam"] - prev["lam"]) ** 2).sum())
+    with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+        h.iterate(7, beta, GAMMA)
+        m = h.merit()[0]
+    assert abs(m[0] - L) <= rtol * abs(L)
+    assert abs(m[1] - psi) <= rtol * abs(psi)
+
+
+def test_solve_without_rejections_equals_iterate(pgo):
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    with pgo.PoseGraph.from_graph(g) as h:
+        b, done, conv = h.solve(200, 50, GAMMA, beta, tol=0.0, beta_growth=2.0)
+        a = h.state()
+    assert done[0] == 200 and not conv[0] and b[0] == beta
+    with pgo.PoseGraph.from_graph(g) as h:
+        h.iterate(200, beta, GAMMA)
+        assert np.array_equal(h.state(), a)
+
+
+def test_solve_stopping_rule(pgo):
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    tol = 1e-4
+    with pgo.PoseGraph.from_graph(g) as h:
+        _, done, conv = h.solve(20000, 10, GAMMA, beta, tol=tol, beta_growth=1.0)
+        e = h.residuals()[0, 2]
+    assert conv[0] and e < tol and done[0] < 20000
+    # one chunk earlier the residual was still above tol
+    with pgo.PoseGraph.from_graph(g) as h:
+        h.iterate(int(done[0]) - 10, beta, GAMMA)
+        assert h.residuals()[0, 2] >= tol
+
+
+def test_penalty_check_rescues_a_diverging_graph(pgo):
+    """Graph 106 of the batch diverges with beta = 0.01 abar (the FP64 oracle
+    diverges too); with the merit check the penalty grows and the cost falls."""
+    b = S.batched(4096, first=106, count=1)
+    g = b.graphs[0]
+    beta0 = 0.01 * abar(g)
+    with pgo.PoseGraph.from_graph(g) as h:
+        c0 = h.cost()[0]
+        h.iterate(600, beta0, GAMMA)
+        c_fixed = h.cost()[0]
+    assert not c_fixed < c0
+    with pgo.PoseGraph.from_graph(g) as h:
+        bfin, done, _ = h.solve(600, 50, GAMMA, beta0, tol=0.0, beta_growth=2.0)
+        c_adapt = h.cost()[0]
+        psi = h.merit()[0, 1]
+    assert bfin[0] > beta0 and done[0] == 600
+    assert c_adapt < 1e-2 * c0 and np.isfinite(psi)
+
+
+def test_batched_solve_matches_single_solves(pgo):
+    b = S.batched(4096, first=100, count=8)
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs])
+    voff, _ = b.offsets()
+    for prec in ("fp64", "fp32"):
+        with pgo.PoseGraph.from_batch(b, precision=prec) as h:
+            bb, done, conv = h.solve(300, 50, GAMMA, betas, tol=1e-3, beta_growth=2.0)
+            allst = h.state()
+        for k, gr in enumerate(b.graphs):
+            with pgo.PoseGraph.from_graph(gr, precision=prec) as h1:
+                b1, d1, c1 = h1.solve(300, 50, GAMMA, betas[k], tol=1e-3, beta_growth=2.0)
+                assert b1[0] == bb[k] and d1[0] == done[k] and c1[0] == conv[k]
+                assert np.array_equal(h1.state(), allst[voff[k]:voff[k + 1]]), (prec, k)
+
+
+def test_solve_argument_checks(pgo):
+    g = S.make_config("circle-100")
+    with pgo.PoseGraph.from_graph(g) as h:
+        for args in ((100, 30, GAMMA, 0.0, 2.0, 1.0), (100, 50, 2.0, 0.0, 2.0, 1.0),
+                     (100, 50, GAMMA, 0.0, 0.5, 1.0), (100, 50, GAMMA, 0.0, 2.0, -1.0)):
+            with pytest.raises(pgo.PgoError):
+                pgo.pgo_solve(h.h, *args)
