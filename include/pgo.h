@@ -212,6 +212,50 @@ pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* p
  */
 pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps);
 
+/*
+ * Differentiation of K unrolled sweeps (reverse mode written by hand).
+ *
+ * pgo_set_edge_params -- replace edge parameters in place (caller edge
+ * order, device FP64 pointers; NULL keeps the current values): kappa (m),
+ * tau (m), tm (m x 3), omega (m x 3).  omega is a right perturbation of each
+ * measured rotation, R~_e Exp(omega_e), applied to the prepared quaternion
+ * of pgo_create: q~_e = q~0_e [cos(|w|/2), sin(|w|/2) w/|w|].  Values are
+ * checked (kappa, tau finite and > 0; tm, omega finite): PGO_EINVAL names
+ * the first bad entry.  The graph structure is unchanged; a recorded
+ * forward pass is discarded.  Synchronises the stream.
+ */
+pgo_status pgo_set_edge_params(pgo_graph* g, const double* kappa_dev, const double* tau_dev,
+                               const double* tm_dev, const double* omega_dev);
+
+/* Put the state back to the initial point of pgo_create (q = p^0, s = t^0,
+ * lambda = z = 0). */
+pgo_status pgo_reset_state(pgo_graph* g);
+
+/* The state as n x 21 doubles written to a device buffer (asynchronous). */
+pgo_status pgo_get_state_dev(pgo_graph* g, double* state_dev);
+
+/*
+ * pgo_forward_record -- run K >= 1 sweeps (scalar beta, gamma in (0,2))
+ * from the current state, keeping the state every C >= 1 sweeps (and at K)
+ * so that pgo_adjoint can recompute the sweeps in between.  Device memory:
+ * (ceil(K/C) + C + 2) state copies.
+ */
+pgo_status pgo_forward_record(pgo_graph* g, int32_t K, double beta, double gamma, int32_t C);
+
+/*
+ * pgo_adjoint -- gradients of a scalar loss L(x^K) through the recorded
+ * sweeps.  dL_dstate: device n x 21 FP64, dL/dx^K in the state layout.
+ * Outputs (device FP64, caller edge order, any may be NULL): g_kappa (m),
+ * g_tau (m), g_tm (m x 3), g_omega (m x 3, derivative with respect to the
+ * omega of pgo_set_edge_params at its current value), dL_dstate0 (n x 21,
+ * dL/dx^0).  Each graph segment of C sweeps is recomputed from its
+ * checkpoint; the reverse sweep runs in the handle's precision and sums
+ * edge gradients in FP64.  Leaves the state at x^K.  PGO_ESTATE if no
+ * forward pass is recorded.  Synchronises the stream.
+ */
+pgo_status pgo_adjoint(pgo_graph* g, const double* dL_dstate, double* g_kappa, double* g_tau,
+                       double* g_tm, double* g_omega, double* dL_dstate0);
+
 /* Release the handle and its device memory.  NULL is ignored. */
 void pgo_destroy(pgo_graph* g);
 

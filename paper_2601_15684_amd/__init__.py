@@ -17,7 +17,8 @@ __all__ = [
     "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
     "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
-    "pgo_destroy", "pgo_last_error", "PoseGraph",
+    "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
+    "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint",
     "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "LIB_PATH",
 ]
 
@@ -67,6 +68,11 @@ _SIGNATURES = {
     "pgo_get_prepared": (C.c_int, [_P, _D, _D]),
     "pgo_info": (C.c_int, [_P, _I64, _I64, _I32, _I32, _I32, _I32]),
     "pgo_autotune": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32]),
+    "pgo_set_edge_params": (C.c_int, [_P, _P, _P, _P, _P]),
+    "pgo_reset_state": (C.c_int, [_P]),
+    "pgo_get_state_dev": (C.c_int, [_P, _P]),
+    "pgo_forward_record": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32]),
+    "pgo_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "pgo_destroy": (None, [_P]),
     "pgo_last_error": (C.c_char_p, []),
 }
@@ -240,6 +246,32 @@ def pgo_get_prepared(h):
 def pgo_autotune(h, beta, gamma, sweeps=10):
     _chk(lib().pgo_autotune(h, float(beta), float(gamma), int(sweeps)))
     return pgo_info(h)
+
+
+def _vp(ptr):
+    return C.c_void_p(int(ptr)) if ptr else None
+
+
+def pgo_set_edge_params(h, kappa_dev=0, tau_dev=0, tm_dev=0, omega_dev=0):
+    """Device pointers (ints, e.g. tensor.data_ptr()) of FP64 arrays; 0 keeps a value."""
+    _chk(lib().pgo_set_edge_params(h, _vp(kappa_dev), _vp(tau_dev), _vp(tm_dev), _vp(omega_dev)))
+
+
+def pgo_reset_state(h):
+    _chk(lib().pgo_reset_state(h))
+
+
+def pgo_get_state_dev(h, state_dev):
+    _chk(lib().pgo_get_state_dev(h, _vp(state_dev)))
+
+
+def pgo_forward_record(h, K, beta, gamma, C):
+    _chk(lib().pgo_forward_record(h, int(K), float(beta), float(gamma), int(C)))
+
+
+def pgo_adjoint(h, dL_dstate_dev, g_kappa=0, g_tau=0, g_tm=0, g_omega=0, dL_dstate0=0):
+    _chk(lib().pgo_adjoint(h, _vp(dL_dstate_dev), _vp(g_kappa), _vp(g_tau), _vp(g_tm),
+                           _vp(g_omega), _vp(dL_dstate0)))
 
 
 def pgo_destroy(h):

@@ -1,0 +1,55 @@
+"""torch.autograd.Function over K unrolled PRADMM sweeps.
+
+The forward pass runs the sweeps in the HIP library from the handle's
+initial point with the given edge parameters; the backward pass is the
+library's hand-written adjoint (pgo_adjoint).  Tensors are float64 on the
+handle's device; the library runs on torch's current stream.
+
+    state = unrolled_pradmm(graph, kappa, tau, tm, omega, K=50, beta=b, gamma=1.4, C=10)
+    loss = ((state[:, 8:11] - t_gt) ** 2).sum()
+    loss.backward()        # kappa.grad, tau.grad, tm.grad, omega.grad
+
+state is n x 21: p(4) q(4) t(3) s(3) lambda(4) z(3) after K sweeps.
+"""
+import torch
+
+from . import (pgo_adjoint, pgo_forward_record, pgo_get_state_dev, pgo_info, pgo_reset_state,
+               pgo_set_edge_params, pgo_set_stream)
+
+
+class UnrolledPRADMM(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, kappa, tau, tm, omega, graph, K, beta, gamma, C):
+        h = graph.h
+        info = pgo_info(h)
+        for name, x, shape in (("kappa", kappa, (info["m"],)), ("tau", tau, (info["m"],)),
+                               ("tm", tm, (info["m"], 3)), ("omega", omega, (info["m"], 3))):
+            if x.dtype != torch.float64 or not x.is_cuda or tuple(x.shape) != shape:
+                raise ValueError(f"{name} must be a float64 CUDA tensor of shape {shape}")
+        kappa, tau, tm, omega = (x.contiguous() for x in (kappa, tau, tm, omega))
+        pgo_set_stream(h, torch.cuda.current_stream().cuda_stream)
+        pgo_set_edge_params(h, kappa.data_ptr(), tau.data_ptr(), tm.data_ptr(), omega.data_ptr())
+        pgo_reset_state(h)
+        pgo_forward_record(h, K, beta, gamma, C)
+        state = torch.empty((info["n"], 21), dtype=torch.float64, device=kappa.device)
+        pgo_get_state_dev(h, state.data_ptr())
+        ctx.graph = graph
+        ctx.m = info["m"]
+        return state
+
+    @staticmethod
+    def backward(ctx, grad_state):
+        h = ctx.graph.h
+        dev = grad_state.device
+        g = grad_state.contiguous().to(torch.float64)
+        gk = torch.empty(ctx.m, dtype=torch.float64, device=dev)
+        gt = torch.empty(ctx.m, dtype=torch.float64, device=dev)
+        gtm = torch.empty((ctx.m, 3), dtype=torch.float64, device=dev)
+        gom = torch.empty((ctx.m, 3), dtype=torch.float64, device=dev)
+        pgo_set_stream(h, torch.cuda.current_stream().cuda_stream)
+        pgo_adjoint(h, g.data_ptr(), gk.data_ptr(), gt.data_ptr(), gtm.data_ptr(), gom.data_ptr(), 0)
+        return gk, gt, gtm, gom, None, None, None, None, None
+
+
+def unrolled_pradmm(graph, kappa, tau, tm, omega, K, beta, gamma, C=10):
+    return UnrolledPRADMM.apply(kappa, tau, tm, omega, graph, K, beta, gamma, C)

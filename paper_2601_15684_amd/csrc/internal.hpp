@@ -138,4 +138,66 @@ hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
                          double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
                          int G, double* out, hipStream_t st);
 
+// ---------------------------------------------------------------------------
+// Reverse mode (adjoint.hip)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StateRef {
+  const Q4<T>* p;
+  const Q4<T>* q;
+  const Q4<T>* lam;
+  const P4<T>* t;
+  const P4<T>* s;
+  const P4<T>* z;
+};
+
+template <typename T>
+struct AdjRef {
+  Q4<T>* pb;
+  Q4<T>* qb;
+  Q4<T>* lb;
+  P4<T>* tb;
+  P4<T>* sb;
+  P4<T>* zb;
+  P4<T>* moS;     // S -> t of the head          (per out-position)
+  P4<T>* miT3;    // T -> s of the tail          (per in-position)
+  Q4<T>* miT4q;   // T -> q of the tail
+  Q4<T>* miT4p;   // T -> p of the tail
+  Q4<T>* moQ4;    // Q -> p of the head          (per out-position)
+  P4<T>* moQ3;    // Q -> t of the head
+  P4<T>* moP;     // P -> t of the head          (per out-position)
+  Q4<T>* miP;     // P -> q of the tail          (per in-position)
+  P4<double>* ga_o;  // d/d(tau t~) (xyz) and d/dtau (u), out-order
+  Q4<double>* gw_o;  // d/d(kappa q~), out-order
+  P4<double>* ga_i;  // in-order
+  Q4<double>* gw_i;
+  double* cqb;
+  double* ctb;
+  double* csb;
+  const int32_t* in2out;
+  const int32_t* out2in;
+};
+
+template <typename T>
+hipError_t launch_reverse_sweep(const DevGraph<T>& g, const StateRef<T>& X, const StateRef<T>& Y,
+                                const AdjRef<T>& A, const SweepParams& sp, int first,
+                                hipStream_t st);
+template <typename T>
+hipError_t launch_reverse_finish(const DevGraph<T>& g, const AdjRef<T>& A, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_io(int n, const AdjRef<T>& A, double* buf, int to_device, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_zero_edges(int64_t m, const AdjRef<T>& A, hipStream_t st);
+template <typename T>
+hipError_t launch_adj_params(int64_t m, const AdjRef<T>& A, const int32_t* pos_out,
+                             const int32_t* pos_in, const int32_t* ei, const int32_t* ej,
+                             const double* tm, const double* kappa, const double* tau,
+                             const Q4<double>* qe0, const double* omega, double* g_kappa,
+                             double* g_tau, double* g_tm, double* g_omega, hipStream_t st);
+hipError_t launch_perturb(int64_t m, const Q4<double>* qe0, const double* omega, Q4<double>* qe,
+                          hipStream_t st);
+hipError_t launch_edge_maps(int64_t m, const int32_t* o_perm, const int32_t* i_perm,
+                            int32_t* pos_out, int32_t* pos_in, int32_t* in2out, int32_t* out2in,
+                            hipStream_t st);
+
 }  // namespace pgo

@@ -1,0 +1,146 @@
+"""GPU tests of the hand-written adjoint of K unrolled sweeps, through the
+C ABI and the torch.autograd.Function: against the oracle's reference
+adjoint (automatic differentiation of the FP64 CPU sweeps) and against FP64
+central finite differences of the library's own FP64 forward pass
+(h = 1e-6, parameters log kappa, log tau, omega, t~)."""
+import numpy as np
+import pytest
+import torch
+
+import pgo_synth as S
+from oracle import prep
+from oracle import pradmm as O
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+
+
+def abar(g):
+    d = np.zeros(g.n)
+    np.add.at(d, g.ei, 2 * (g.tau * (g.tm ** 2).sum(1) + g.kappa))
+    np.add.at(d, g.ej, 2 * g.kappa)
+    return float(d.mean())
+
+
+def cuda(x):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
+
+
+def gpu_grads(pgo, g, K, beta, C, prec, omega=None):
+    from paper_2601_15684_amd.autograd import unrolled_pradmm
+    kappa = cuda(g.kappa).requires_grad_()
+    tau = cuda(g.tau).requires_grad_()
+    tm = cuda(g.tm).requires_grad_()
+    om = cuda(np.zeros((g.m, 3)) if omega is None else omega).requires_grad_()
+    with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+        state = unrolled_pradmm(h, kappa, tau, tm, om, K, beta, GAMMA, C)
+        loss = ((state[:, 8:11] - cuda(g.t_gt)) ** 2).sum()
+        loss.backward()
+    torch.cuda.synchronize()
+    return float(loss), dict(kappa=kappa.grad.cpu().numpy(), tau=tau.grad.cpu().numpy(),
+                             tm=tm.grad.cpu().numpy(), omega=om.grad.cpu().numpy())
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
+@pytest.mark.parametrize("K,C", [(10, 3), (6, 6)])
+def test_adjoint_matches_oracle(pgo, prec, tol, K, C):
+    g = S.grid(4, 3, 3, all_pairs=True, sigma_R=0.05, sigma_t=0.1, seed=0)
+    beta = 0.05 * abar(g)
+    P, p0, t0 = prep.prepare_graph(g)
+    L_ref, ref = O.unrolled_grad(P, p0, t0, K, beta, GAMMA, torch.as_tensor(g.t_gt))
+    L, got = gpu_grads(pgo, g, K, beta, C, prec)
+    assert abs(L - L_ref) <= (1e-10 if prec == "fp64" else 1e-4) * L_ref
+    for k in ("kappa", "tau", "tm", "omega"):
+        assert rel(got[k], ref[k].numpy()) <= tol, (k, rel(got[k], ref[k].numpy()))
+
+
+def test_adjoint_state_gradient_matches_oracle(pgo):
+    g = S.random_small(6, 5, seed=4, sigma_R=0.05, sigma_t=0.1)
+    beta, K = 0.05 * abar(g), 7
+    P, p0, t0 = prep.prepare_graph(g)
+    st = O.init_state(p0, t0)
+    leaves = {k: v.clone().requires_grad_() for k, v in st.items()}
+    s = dict(leaves)
+    for _ in range(K):
+        s = O.sweep(P, s, beta, GAMMA)
+    w = torch.as_tensor(np.random.default_rng(0).standard_normal((g.n, 21)))
+    packed = torch.cat([s[k] for k in ("p", "q", "t", "s", "lam", "z")], 1)
+    (packed * w).sum().backward()
+    ref = torch.cat([leaves[k].grad for k in ("p", "q", "t", "s", "lam", "z")], 1).numpy()
+    with pgo.PoseGraph.from_graph(g) as h:
+        pgo.pgo_forward_record(h.h, K, beta, GAMMA, 3)
+        wd = cuda(w.numpy())
+        d0 = torch.empty((g.n, 21), dtype=torch.float64, device="cuda")
+        pgo.pgo_adjoint(h.h, wd.data_ptr(), 0, 0, 0, 0, d0.data_ptr())
+        torch.cuda.synchronize()
+        got = d0.cpu().numpy()
+    assert rel(got, ref) <= 1e-9
+
+
+def _fd_loss(pgo, h, base, g, K, beta, C):
+    pgo.pgo_set_edge_params(h.h, base["kappa"].data_ptr(), base["tau"].data_ptr(),
+                            base["tm"].data_ptr(), base["omega"].data_ptr())
+    pgo.pgo_reset_state(h.h)
+    pgo.pgo_forward_record(h.h, K, beta, GAMMA, C)
+    st = h.state()
+    return float(((st[:, 8:11] - g.t_gt) ** 2).sum())
+
+
+@pytest.mark.parametrize("omega_scale", [0.0, 0.02])
+def test_adjoint_vs_central_differences_diff_20k(pgo, omega_scale):
+    """The 20k-pose grid, K = 50 unrolled sweeps, checkpoint every 10: FP32
+    and FP64 adjoints against FP64 central differences on 64 random edges."""
+    g = S.make_config("diff-20k")
+    K, C, hstep = 50, 10, 1e-6
+    beta = 0.01 * abar(g)
+    rng = np.random.default_rng(0)
+    omega = omega_scale * rng.standard_normal((g.m, 3))
+    _, g32 = gpu_grads(pgo, g, K, beta, C, "fp32", omega)
+    _, g64 = gpu_grads(pgo, g, K, beta, C, "fp64", omega)
+    edges = rng.choice(g.m, size=64, replace=False)
+    fd = {k: [] for k in ("log_kappa", "log_tau", "omega", "tm")}
+    with pgo.PoseGraph.from_graph(g, precision="fp64") as h:
+        base = dict(kappa=cuda(g.kappa), tau=cuda(g.tau), tm=cuda(g.tm), omega=cuda(omega))
+
+        def loss_with(name, idx, delta, mul=False):
+            b = {k: v.clone() for k, v in base.items()}
+            if mul:
+                b[name][idx] = b[name][idx] * float(np.exp(delta))
+            else:
+                b[name][idx] = b[name][idx] + delta
+            return _fd_loss(pgo, h, b, g, K, beta, C)
+
+        for e in edges:
+            e = int(e)
+            fd["log_kappa"].append((loss_with("kappa", e, hstep, True) - loss_with("kappa", e, -hstep, True)) / (2 * hstep))
+            fd["log_tau"].append((loss_with("tau", e, hstep, True) - loss_with("tau", e, -hstep, True)) / (2 * hstep))
+            for c in range(3):
+                fd["omega"].append((loss_with("omega", (e, c), hstep) - loss_with("omega", (e, c), -hstep)) / (2 * hstep))
+                fd["tm"].append((loss_with("tm", (e, c), hstep) - loss_with("tm", (e, c), -hstep)) / (2 * hstep))
+    for name, grads, tol in (("fp64", g64, 1e-5), ("fp32", g32, 1e-3)):
+        ad = {"log_kappa": grads["kappa"][edges] * g.kappa[edges],
+              "log_tau": grads["tau"][edges] * g.tau[edges],
+              "omega": grads["omega"][edges].ravel(), "tm": grads["tm"][edges].ravel()}
+        for k in fd:
+            assert rel(ad[k], fd[k]) <= tol, (name, k, rel(ad[k], fd[k]))
+    for k in ("kappa", "tau", "tm", "omega"):
+        assert rel(g32[k], g64[k]) <= 1e-3, k
+
+
+def test_adjoint_requires_a_recorded_pass(pgo):
+    g = S.make_config("circle-100")
+    with pgo.PoseGraph.from_graph(g) as h:
+        d = torch.zeros((g.n, 21), dtype=torch.float64, device="cuda")
+        with pytest.raises(pgo.PgoError) as ex:
+            pgo.pgo_adjoint(h.h, d.data_ptr())
+        assert ex.value.name == "PGO_ESTATE"
+        bad = cuda(g.kappa)
+        bad[3] = -1.0
+        with pytest.raises(pgo.PgoError) as ex:
+            pgo.pgo_set_edge_params(h.h, bad.data_ptr(), 0, 0, 0)
+        assert ex.value.name == "PGO_EINVAL" and "kappa entry 3" in str(ex.value)
