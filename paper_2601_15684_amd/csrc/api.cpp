@@ -89,6 +89,7 @@ struct pgo_graph {
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
+  int graph_regs = 1;  // per-graph kernel keeps own-only values in registers
   bool have_prev = false;
   // captured launch sequence of the per-phase schedule
   hipGraphExec_t gexec = nullptr;
@@ -485,7 +486,8 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
                  per_graph ? g->beta_dev : nullptr, masked ? g->active_dev : nullptr};
   const DevGraph<T> d = view<T>(g);
   if (sched == PGO_SCHED_GRAPH) {
-    HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->stream));
+    HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->max_n,
+                                  g->graph_regs, g->stream));
     return PGO_OK;
   }
   // per-phase launches, captured once into a HIP graph per (k, beta, gamma, block)

@@ -61,9 +61,12 @@ struct SweepParams {
 template <typename T>
 hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& sp, int block,
                                hipStream_t st);
+// regs != 0 selects the variant that holds each thread's own-only values in
+// registers (when max_n <= 8 * block).
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
-                               int G, int k, const SweepParams& sp, int block, hipStream_t st);
+                               int G, int k, const SweepParams& sp, int block, int max_n, int regs,
+                               hipStream_t st);
 
 // Per-graph snapshot restore: every vertex of a graph with flag[g] != 0 gets
 // its state (p, q, lambda, t, s, z) back from the snapshot arrays.

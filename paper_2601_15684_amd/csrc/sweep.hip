@@ -21,6 +21,10 @@
 //
 // Inside a phase a vertex reads only values written by earlier phases, and
 // writes only its own slots, so all updates are in place and race-free.
+// Only three barriers per sweep are needed: P reads no neighbour's s (only
+// neighbours' t and q, final before S starts, and its own new s), so the S
+// of sweep k and the P of sweep k+1 run as one phase.  A k-sweep launch is
+// P, then k times (Q, T, S+P), the last S+P being a plain S.
 // Per-vertex sums run over the CSR/CSC segment in edge order, one thread per
 // vertex, with no atomics: results are deterministic and identical between
 // the per-phase launches and the per-graph persistent kernel.
@@ -46,9 +50,10 @@ __device__ __forceinline__ A l1(const Q4<A>& t) {
 // Sum of the edge terms of the P phase, in accumulation type A.  mag collects
 // the L1 size of every term (used only by the FP32 cancellation check).
 template <typename A, typename T, bool kMag>
-__device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, A& mag) {
-  const Q4<A> qi = cvt<A>(g.q[i]);
-  const V3<A> si = v3a<A>(g.s[i]);
+__device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, const Q4<T>& q_i,
+                                            const P4<T>& s_i, A& mag) {
+  const Q4<A> qi = cvt<A>(q_i);
+  const V3<A> si = v3a<A>(s_i);
   Q4<A> acc = {A(0), A(0), A(0), A(0)};
   const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
   for (int e = o0; e < o1; ++e) {
@@ -71,29 +76,36 @@ __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, A& mag)
 }
 
 template <typename A, typename T>
-__device__ __forceinline__ Q4<A> p_vector(const DevGraph<T>& g, int i, const Q4<A>& acc,
-                                          const SweepParams& sp) {
-  const Q4<A> qi = cvt<A>(g.q[i]), li = cvt<A>(g.lam[i]), pi = cvt<A>(g.p[i]);
+__device__ __forceinline__ Q4<A> p_vector(const Q4<A>& acc, const Q4<T>& q_i, const Q4<T>& p_i,
+                                          const Q4<T>& lam, const SweepParams& sp) {
+  const Q4<A> qi = cvt<A>(q_i), li = cvt<A>(lam), pi = cvt<A>(p_i);
   const A b = A(sp.beta), h = A(sp.h1);
   return {A(2) * acc.w + b * qi.w + li.w + h * pi.w, A(2) * acc.x + b * qi.x + li.x + h * pi.x,
           A(2) * acc.y + b * qi.y + li.y + h * pi.y, A(2) * acc.z + b * qi.z + li.z + h * pi.z};
 }
 
+// The own-only values of a vertex (never read by a neighbour): the
+// multipliers lambda_i, z_i and the constants cQ_i, cT_i, cS_i.  They are
+// passed in by the caller, which keeps them in memory (per-phase launches)
+// or in registers across all sweeps of a launch (per-graph kernel).
+// P update of vertex i from its own values q_i, s_i, p_i, lambda_i (passed
+// in, so a caller that has them in registers does not reload them).
 template <typename T>
-__device__ __forceinline__ void vertex_P(const DevGraph<T>& g, int i, const SweepParams& sp) {
+__device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                             const Q4<T>& qi, const P4<T>& si, const Q4<T>& pi,
+                                             const Q4<T>& li) {
   constexpr bool kF32 = sizeof(T) == 4;
   T mag = T(0);
-  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, i, mag);
-  const Q4<T> v = p_vector<T, T>(g, i, acc, sp);
+  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, i, qi, si, mag);
+  const Q4<T> v = p_vector<T, T>(acc, qi, pi, li, sp);
   const T nrm = sqrt(v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z);
   if (kF32) {
     // FP64 island: when the sum cancels, redo it in double.
-    const Q4<T> qi = g.q[i], li = g.lam[i], pi = g.p[i];
     const T tot = T(2) * mag + T(sp.beta) * l1(qi) + l1(li) + T(sp.h1) * l1(pi);
     if (!(nrm >= T(1e-3) * tot)) {
       double dm = 0.0;
-      const Q4<double> dacc = p_edge_sum<double, T, false>(g, i, dm);
-      const Q4<double> dv = p_vector<double, T>(g, i, dacc, sp);
+      const Q4<double> dacc = p_edge_sum<double, T, false>(g, i, qi, si, dm);
+      const Q4<double> dv = p_vector<double, T>(dacc, qi, pi, li, sp);
       const double dn = sqrt(dv.w * dv.w + dv.x * dv.x + dv.y * dv.y + dv.z * dv.z);
       if (dn > 0.0)
         g.p[i] = Q4<T>{T(dv.w / dn), T(dv.x / dn), T(dv.y / dn), T(dv.z / dn)};
@@ -104,9 +116,15 @@ __device__ __forceinline__ void vertex_P(const DevGraph<T>& g, int i, const Swee
 }
 
 template <typename T>
+__device__ __forceinline__ void vertex_P(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                         const Q4<T>& li) {
+  vertex_P_own(g, i, sp, g.q[i], g.s[i], g.p[i], li);
+}
+
+template <typename T>
 __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         bool save) {
-  const Q4<T> pi = g.p[i], qi = g.q[i], li = g.lam[i];
+                                         bool save, Q4<T>& lam, T cQ) {
+  const Q4<T> pi = g.p[i], qi = g.q[i], li = lam;
   const V3<T> si = v3(g.s[i]);
   Q4<T> acc = {T(0), T(0), T(0), T(0)};
   const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
@@ -120,7 +138,7 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const Swee
     acc4(acc, qmul(g.p[j], qconj(g.o_w[e])));
   }
   const T b = T(sp.beta), h = T(sp.h2);
-  const T a = g.cQ[i] + b + h;
+  const T a = cQ + b + h;
   const Q4<T> qn = {(T(2) * acc.w + b * pi.w - li.w + h * qi.w) / a,
                     (T(2) * acc.x + b * pi.x - li.x + h * qi.x) / a,
                     (T(2) * acc.y + b * pi.y - li.y + h * qi.y) / a,
@@ -131,13 +149,13 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const Swee
     g.lam_prev[i] = li;
   }
   g.q[i] = qn;
-  g.lam[i] = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x),
-                   li.y - gb * (pi.y - qn.y), li.z - gb * (pi.z - qn.z)};
+  lam = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x), li.y - gb * (pi.y - qn.y),
+              li.z - gb * (pi.z - qn.z)};
 }
 
 template <typename T>
 __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         bool save) {
+                                         bool save, const V3<T>& zi, T cT) {
   V3<T> acc = {T(0), T(0), T(0)};
   const int n0 = g.i_ptr[i], n1 = g.i_ptr[i + 1];
   for (int e = n0; e < n1; ++e) {
@@ -149,9 +167,9 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const Swee
     acc.y += u.u * sl.y + c.y;
     acc.z += u.u * sl.z + c.z;
   }
-  const P4<T> ti = g.t[i], si = g.s[i], zi = g.z[i];
+  const P4<T> ti = g.t[i], si = g.s[i];
   const T b = T(sp.beta), h = T(sp.h3);
-  const T a = g.cT[i] + b + h;
+  const T a = cT + b + h;
   if (save) g.t_prev[i] = ti;
   g.t[i] = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
                  (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
@@ -160,7 +178,8 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const Swee
 
 template <typename T>
 __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         bool save) {
+                                         bool save, V3<T>& z, T cS, Q4<T>* p_out = nullptr,
+                                         Q4<T>* q_out = nullptr, P4<T>* s_out = nullptr) {
   const Q4<T> pi = g.p[i], qi = g.q[i];
   V3<T> acc = {T(0), T(0), T(0)};
   const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
@@ -173,20 +192,60 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
     acc.y += u.u * tj.y - c.y;
     acc.z += u.u * tj.z - c.z;
   }
-  const P4<T> ti = g.t[i], si = g.s[i], zi = g.z[i];
+  const P4<T> ti = g.t[i], si = g.s[i];
+  const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);
-  const T a = g.cS[i] + b + h;
+  const T a = cS + b + h;
   const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
                     (T(2) * acc.y + b * ti.y - zi.y + h * si.y) / a,
                     (T(2) * acc.z + b * ti.z - zi.z + h * si.z) / a};
   const T gb = T(sp.gamma * sp.beta);
   if (save) {
     g.s_prev[i] = si;
-    g.z_prev[i] = zi;
+    g.z_prev[i] = pad3(zi);
   }
   g.s[i] = pad3(sn);
-  g.z[i] = P4<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
-                 zi.z - gb * (ti.z - sn.z), T(0)};
+  z = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  if (p_out) {
+    *p_out = pi;
+    *q_out = qi;
+    *s_out = pad3(sn);
+  }
+}
+
+// S of one sweep fused with P of the next: P reads no neighbour's s, only
+// its own new s and neighbour values finished before S began, so no barrier
+// is needed between them and P reuses S's own values.
+template <typename T>
+__device__ __forceinline__ void vertex_SP(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                          V3<T>& z, T cS, const Q4<T>& li) {
+  Q4<T> pi, qi;
+  P4<T> si;
+  vertex_S(g, i, sp, false, z, cS, &pi, &qi, &si);
+  vertex_P_own(g, i, sp, qi, si, pi, li);
+}
+
+// phase bodies with the own-only values kept in memory
+template <int PH, typename T>
+__device__ __forceinline__ void phase_mem(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                          bool save) {
+  if (PH == 0) vertex_P(g, i, sp, g.lam[i]);
+  if (PH == 1) {
+    Q4<T> l = g.lam[i];
+    vertex_Q(g, i, sp, save, l, g.cQ[i]);
+    g.lam[i] = l;
+  }
+  if (PH == 2) vertex_T(g, i, sp, save, v3(g.z[i]), g.cT[i]);
+  if (PH == 3) {
+    V3<T> z = v3(g.z[i]);
+    vertex_S(g, i, sp, save, z, g.cS[i]);
+    g.z[i] = pad3(z);
+  }
+  if (PH == 4) {  // S of this sweep + P of the next
+    V3<T> z = v3(g.z[i]);
+    vertex_SP(g, i, sp, z, g.cS[i], g.lam[i]);
+    g.z[i] = pad3(z);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -210,10 +269,7 @@ __global__ void k_phase(DevGraph<T> g, SweepParams sp, int save) {
   if (i >= g.n) return;
   if (sp.active && !sp.active[g.gid[i]]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[g.gid[i]];
-  if (PH == 0) vertex_P(g, i, sp);
-  if (PH == 1) vertex_Q(g, i, sp, save != 0);
-  if (PH == 2) vertex_T(g, i, sp, save != 0);
-  if (PH == 3) vertex_S(g, i, sp, save != 0);
+  phase_mem<PH, T>(g, i, sp, save != 0);
 }
 
 template <typename T>
@@ -222,12 +278,15 @@ hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& s
   if (g.n <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
   const int nb = (g.n + block - 1) / block;
+  hipLaunchKernelGGL((k_phase<0, T>), dim3(nb), dim3(block), 0, st, g, sp, 0);
   for (int it = 0; it < k; ++it) {
     const int save = it == k - 1;
-    hipLaunchKernelGGL((k_phase<0, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
     hipLaunchKernelGGL((k_phase<1, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
     hipLaunchKernelGGL((k_phase<2, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
-    hipLaunchKernelGGL((k_phase<3, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    if (save)
+      hipLaunchKernelGGL((k_phase<3, T>), dim3(nb), dim3(block), 0, st, g, sp, 1);
+    else
+      hipLaunchKernelGGL((k_phase<4, T>), dim3(nb), dim3(block), 0, st, g, sp, 0);
     const hipError_t err = hipGetLastError();
     if (err != hipSuccess) return err;
   }
@@ -247,24 +306,31 @@ __global__ void k_graph_sweeps(DevGraph<T> g, const int32_t* __restrict__ voff,
   const int v0 = voff[gr], v1 = voff[gr + 1];
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<0, T>(g, i, sp, false);
+  __syncthreads();
   for (int it = 0; it < k; ++it) {
     const bool save = it == k - 1;
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_P(g, i, sp);
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<1, T>(g, i, sp, save);
     __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_Q(g, i, sp, save);
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<2, T>(g, i, sp, save);
     __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_T(g, i, sp, save);
-    __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_S(g, i, sp, save);
+    if (save) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<3, T>(g, i, sp, true);
+    } else {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<4, T>(g, i, sp, false);
+    }
     __syncthreads();
   }
 }
 
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
-                               int G, int k, const SweepParams& sp, int block, hipStream_t st) {
+                               int G, int k, const SweepParams& sp, int block, int max_n,
+                               int regs, hipStream_t st) {
   if (G <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  (void)max_n;
+  (void)regs;
   hipLaunchKernelGGL((k_graph_sweeps<T>), dim3(G), dim3(block), 0, st, g, voff, order, k, sp);
   return hipGetLastError();
 }
@@ -308,9 +374,9 @@ template hipError_t launch_phase_sweeps<double>(const DevGraph<double>&, int,
                                                 const SweepParams&, int, hipStream_t);
 template hipError_t launch_graph_sweeps<float>(const DevGraph<float>&, const int32_t*,
                                                const int32_t*, int, int, const SweepParams&, int,
-                                               hipStream_t);
+                                               int, int, hipStream_t);
 template hipError_t launch_graph_sweeps<double>(const DevGraph<double>&, const int32_t*,
                                                 const int32_t*, int, int, const SweepParams&, int,
-                                                hipStream_t);
+                                                int, int, hipStream_t);
 
 }  // namespace pgo
