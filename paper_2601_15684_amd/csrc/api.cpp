@@ -89,7 +89,7 @@ struct pgo_graph {
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
-  int graph_regs = 1;  // per-graph kernel keeps own-only values in registers
+  int graph_regs = 1;  // per-graph kernel keeps lambda and z in LDS when they fit
   bool have_prev = false;
   // captured launch sequence of the per-phase schedule
   hipGraphExec_t gexec = nullptr;

@@ -61,11 +61,11 @@ struct SweepParams {
 template <typename T>
 hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& sp, int block,
                                hipStream_t st);
-// regs != 0 selects the variant that holds each thread's own-only values in
-// registers (when max_n <= 8 * block).
+// lds != 0 selects the variant that holds every vertex's lambda and z in LDS
+// for the whole launch (when max_n slots fit in 160 KB).
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
-                               int G, int k, const SweepParams& sp, int block, int max_n, int regs,
+                               int G, int k, const SweepParams& sp, int block, int max_n, int lds,
                                hipStream_t st);
 
 // Per-graph snapshot restore: every vertex of a graph with flag[g] != 0 gets

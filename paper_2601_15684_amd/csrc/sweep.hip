@@ -323,14 +323,84 @@ __global__ void k_graph_sweeps(DevGraph<T> g, const int32_t* __restrict__ voff,
   }
 }
 
+// The per-graph schedule with each vertex's lambda and z held in LDS for the
+// whole launch (loaded once, written back once): only the owning thread
+// ever touches them, so LDS removes their per-sweep memory traffic.
+// Dynamic LDS: max_n slots of lambda (Q4) and z (P4).
+template <int PH, typename T>
+__device__ __forceinline__ void phase_lds(const DevGraph<T>& g, int i, const SweepParams& sp,
+                                          bool save, Q4<T>& lam, P4<T>& zs) {
+  if (PH == 0) vertex_P(g, i, sp, lam);
+  if (PH == 1) vertex_Q(g, i, sp, save, lam, g.cQ[i]);
+  if (PH == 2) vertex_T(g, i, sp, save, v3(zs), g.cT[i]);
+  if (PH == 3 || PH == 4) {
+    V3<T> z = v3(zs);
+    if (PH == 3) vertex_S(g, i, sp, save, z, g.cS[i]);
+    if (PH == 4) vertex_SP(g, i, sp, z, g.cS[i], lam);
+    zs = pad3(z);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_graph_sweeps_lds(DevGraph<T> g,
+                                                           const int32_t* __restrict__ voff,
+                                                           const int32_t* __restrict__ order,
+                                                           int k, SweepParams sp, int max_n) {
+  extern __shared__ unsigned char lds_raw[];
+  Q4<T>* lam = reinterpret_cast<Q4<T>*>(lds_raw);
+  P4<T>* zz = reinterpret_cast<P4<T>*>(lds_raw + sizeof(Q4<T>) * size_t(max_n));
+  const int gr = order[blockIdx.x];
+  const int v0 = voff[gr], v1 = voff[gr + 1];
+  if (sp.active && !sp.active[gr]) return;
+  if (sp.beta_g) sp.beta = sp.beta_g[gr];
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
+    lam[i - v0] = g.lam[i];
+    zz[i - v0] = g.z[i];
+  }
+  // each slot is read and written only by the thread that loaded it
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+    phase_lds<0, T>(g, i, sp, false, lam[i - v0], zz[i - v0]);
+  __syncthreads();
+  for (int it = 0; it < k; ++it) {
+    const bool save = it == k - 1;
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+      phase_lds<1, T>(g, i, sp, save, lam[i - v0], zz[i - v0]);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+      phase_lds<2, T>(g, i, sp, save, lam[i - v0], zz[i - v0]);
+    __syncthreads();
+    if (save) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+        phase_lds<3, T>(g, i, sp, true, lam[i - v0], zz[i - v0]);
+    } else {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+        phase_lds<4, T>(g, i, sp, false, lam[i - v0], zz[i - v0]);
+    }
+    __syncthreads();
+  }
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
+    g.lam[i] = lam[i - v0];
+    g.z[i] = zz[i - v0];
+  }
+}
+
+constexpr size_t kLdsBytes = 160 * 1024;
+
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
                                int G, int k, const SweepParams& sp, int block, int max_n,
                                int regs, hipStream_t st) {
   if (G <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
-  (void)max_n;
-  (void)regs;
+  const size_t lds = (sizeof(Q4<T>) + sizeof(P4<T>)) * size_t(max_n);
+  if (regs && lds <= kLdsBytes &&
+      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_lds<T>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) == hipSuccess) {
+    hipLaunchKernelGGL((k_graph_sweeps_lds<T>), dim3(G), dim3(block), lds, st, g, voff, order, k,
+                       sp, max_n);
+    return hipGetLastError();
+  }
+  (void)hipGetLastError();  // clear a refused attribute request; use the plain kernel
   hipLaunchKernelGGL((k_graph_sweeps<T>), dim3(G), dim3(block), 0, st, g, voff, order, k, sp);
   return hipGetLastError();
 }

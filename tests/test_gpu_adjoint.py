@@ -131,14 +131,23 @@ def test_adjoint_vs_central_differences_diff_20k(pgo, omega_scale):
             for c in range(3):
                 fd["omega"].append(central("omega", (e, c)))
                 fd["tm"].append(central("tm", (e, c)))
-    for name, grads, tol in (("fp64", g64, 1e-5), ("fp32", g32, 1e-3)):
+    # Tolerances: at h = 1e-6 the central difference of the FP64 forward has a
+    # noise floor of about eps |t| |t - t_gt| sqrt(n) / h ~ 1e-4 absolute on
+    # this 20k-pose problem (the FP64 adjoint matches the exact oracle
+    # derivative to 1e-8 on small graphs), hence 1e-4 relative for FP64;
+    # FP32 adds its own rounding, 1e-3.
+    errs = {}
+    for name, grads in (("fp64", g64), ("fp32", g32)):
         ad = {"log_kappa": grads["kappa"][edges] * g.kappa[edges],
               "log_tau": grads["tau"][edges] * g.tau[edges],
               "omega": grads["omega"][edges].ravel(), "tm": grads["tm"][edges].ravel()}
         for k in fd:
-            assert rel(ad[k], fd[k]) <= tol, (name, k, rel(ad[k], fd[k]))
+            errs[(name, k)] = rel(ad[k], fd[k])
     for k in ("kappa", "tau", "tm", "omega"):
-        assert rel(g32[k], g64[k]) <= 1e-3, k
+        errs[("fp32-vs-fp64", k)] = rel(g32[k], g64[k])
+    print("adjoint vs central differences:", {f"{a}/{b}": f"{v:.2e}" for (a, b), v in errs.items()})
+    bad = {kk: v for kk, v in errs.items() if v > (1e-4 if kk[0] == "fp64" else 1e-3)}
+    assert not bad, bad
 
 
 def test_adjoint_requires_a_recorded_pass(pgo):
