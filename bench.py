@@ -297,6 +297,7 @@ def main():
                          "median_final_over_initial": float(np.median(F1 / F0)),
                          "worst_final_over_initial": float(np.max(F1 / F0)),
                          "graphs_beta_raised": int(np.sum(r32["beta"] > betas)),
+                         "max_beta_over_initial": float(np.max(r32["beta"] / betas)),
                          "sweeps_per_graph": int(r32["accepted"].max())},
     }
     r64 = None

@@ -170,10 +170,13 @@ pgo_status pgo_merit(pgo_graph* g, double* out);
  * launch per chunk for all graphs still running).  After each chunk, for
  * every running graph:
  *   - if beta_growth > 1 and its merit Psi (see pgo_merit) rose over the
- *     chunk, the chunk is undone for that graph (state restored on the
+ *     chunk by more than the rounding jitter of the state (1e-12 |Psi| in
+ *     FP64, 1e-7 |Psi| in FP32), or the chunk left a non-finite value in
+ *     the graph, the chunk is undone for that graph (state restored on the
  *     device) and its beta multiplied by beta_growth (at most 40 times per
- *     call; Theorem 1 asks beta above a threshold the paper does not give,
- *     and the experiments adjust beta by checking exactly this descent);
+ *     call and never past 1e30; Theorem 1 asks beta above a threshold the
+ *     paper does not give, and the experiments adjust beta by checking
+ *     exactly this descent);
  *   - otherwise the chunk is accepted; the graph stops when its residual
  *     e (App. E.1) is below tol (tol <= 0: never) or after max_sweeps
  *     accepted sweeps.
@@ -181,6 +184,8 @@ pgo_status pgo_merit(pgo_graph* g, double* out);
  *   beta        in/out, G values > 0 (the penalties reached)
  *   sweeps_done out, G values (accepted sweeps), may be NULL
  *   converged   out, G values (1 where e < tol stopped the graph), may be NULL
+ * PGO_ENUMERIC when a graph reaches a non-finite state that cannot be undone
+ * (beta_growth == 1, or its beta can grow no further).
  * Synchronises the stream once per chunk.
  */
 pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, double gamma,

@@ -3,7 +3,10 @@
 The forward pass runs the sweeps in the HIP library from the handle's
 initial point with the given edge parameters; the backward pass is the
 library's hand-written adjoint (pgo_adjoint).  Tensors are float64 on the
-handle's device; the library runs on torch's current stream.
+handle's device.  The library runs on a side stream of its own that first
+waits for torch's current stream, and torch's current stream waits for it
+before either call returns, so the calls are ordered with surrounding torch
+work whichever stream (the legacy default one included) is current.
 
     state = unrolled_pradmm(graph, kappa, tau, tm, omega, K=50, beta=b, gamma=1.4, C=10)
     loss = ((state[:, 8:11] - t_gt) ** 2).sum()
@@ -17,6 +20,19 @@ from . import (pgo_adjoint, pgo_forward_record, pgo_get_state_dev, pgo_info, pgo
                pgo_set_edge_params, pgo_set_stream)
 
 
+_SIDE = {}
+
+
+def _enter(h, device):
+    cur = torch.cuda.current_stream(device)
+    side = _SIDE.get(device.index)
+    if side is None:
+        side = _SIDE[device.index] = torch.cuda.Stream(device=device)
+    side.wait_stream(cur)
+    pgo_set_stream(h, side.cuda_stream)
+    return cur, side
+
+
 class UnrolledPRADMM(torch.autograd.Function):
     @staticmethod
     def forward(ctx, kappa, tau, tm, omega, graph, K, beta, gamma, C):
@@ -27,12 +43,13 @@ class UnrolledPRADMM(torch.autograd.Function):
             if x.dtype != torch.float64 or not x.is_cuda or tuple(x.shape) != shape:
                 raise ValueError(f"{name} must be a float64 CUDA tensor of shape {shape}")
         kappa, tau, tm, omega = (x.contiguous() for x in (kappa, tau, tm, omega))
-        pgo_set_stream(h, torch.cuda.current_stream().cuda_stream)
+        state = torch.empty((info["n"], 21), dtype=torch.float64, device=kappa.device)
+        cur, side = _enter(h, kappa.device)
         pgo_set_edge_params(h, kappa.data_ptr(), tau.data_ptr(), tm.data_ptr(), omega.data_ptr())
         pgo_reset_state(h)
         pgo_forward_record(h, K, beta, gamma, C)
-        state = torch.empty((info["n"], 21), dtype=torch.float64, device=kappa.device)
         pgo_get_state_dev(h, state.data_ptr())
+        cur.wait_stream(side)
         ctx.graph = graph
         ctx.m = info["m"]
         return state
@@ -46,8 +63,9 @@ class UnrolledPRADMM(torch.autograd.Function):
         gt = torch.empty(ctx.m, dtype=torch.float64, device=dev)
         gtm = torch.empty((ctx.m, 3), dtype=torch.float64, device=dev)
         gom = torch.empty((ctx.m, 3), dtype=torch.float64, device=dev)
-        pgo_set_stream(h, torch.cuda.current_stream().cuda_stream)
+        cur, side = _enter(h, dev)
         pgo_adjoint(h, g.data_ptr(), gk.data_ptr(), gt.data_ptr(), gtm.data_ptr(), gom.data_ptr(), 0)
+        cur.wait_stream(side)
         return gk, gt, gtm, gom, None, None, None, None, None
 
 

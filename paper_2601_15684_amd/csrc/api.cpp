@@ -431,8 +431,7 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   if (he != hipSuccess) return bail(hip_fail(he, "align"));
   if ((s = dalloc(g, &g->qe0, size_t(m))) != PGO_OK) return bail(s);
   if (m) {
-    he = hipMemcpyAsync(g->qe0, g->qe, sizeof(Q4<double>) * size_t(m), hipMemcpyDeviceToDevice,
-                        g->stream);
+    he = launch_copy(g->qe0, g->qe, sizeof(Q4<double>) * size_t(m), g->stream);
     if (he != hipSuccess) return bail(hip_fail(he, "copy"));
   }
   {
@@ -552,7 +551,9 @@ pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int 
   return s;
 }
 
-pgo_status reduce(pgo_graph* g, std::vector<double>& out) {
+// Per-graph reduction values (RedIdx order).  Unless allow_nonfinite, a
+// non-finite value anywhere is reported as PGO_ENUMERIC.
+pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite = false) {
   HIPCHK(hipSetDevice(g->device));
   EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau};
   hipError_t he;
@@ -569,9 +570,16 @@ pgo_status reduce(pgo_graph* g, std::vector<double>& out) {
   HIPCHK(hipMemcpyAsync(out.data(), g->red_out, out.size() * sizeof(double),
                         hipMemcpyDeviceToHost, g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
-  for (double v : out)
-    if (!std::isfinite(v)) return fail(PGO_ENUMERIC, "the state contains a non-finite value");
+  if (!allow_nonfinite)
+    for (double v : out)
+      if (!std::isfinite(v)) return fail(PGO_ENUMERIC, "the state contains a non-finite value");
   return PGO_OK;
+}
+
+bool finite_graph(const std::vector<double>& r, int32_t j) {
+  for (int k = 0; k < kRedVals; ++k)
+    if (!std::isfinite(r[size_t(kRedVals) * j + k])) return false;
+  return true;
 }
 
 pgo_status ensure_iobuf(pgo_graph* g) {
@@ -602,7 +610,7 @@ pgo_status snapshot_or_restore(pgo_graph* g, bool restore) {
         pgo_status s = dalloc_bytes(g, &g->snap[k], bytes);
         if (s != PGO_OK) return s;
       }
-      HIPCHK(hipMemcpyAsync(g->snap[k], cur[k], bytes, hipMemcpyDeviceToDevice, g->stream));
+      HIPCHK(launch_copy(g->snap[k], cur[k], bytes, g->stream));
     }
     return PGO_OK;
   }
@@ -654,7 +662,7 @@ void** state_ptrs(pgo_graph* g, void** out6) {
 
 pgo_status copy_state(pgo_graph* g, void* const* dst, void* const* src) {
   for (int k = 0; k < 6; ++k)
-    HIPCHK(hipMemcpyAsync(dst[k], src[k], state_bytes(g), hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(launch_copy(dst[k], src[k], state_bytes(g), g->stream));
   return PGO_OK;
 }
 
@@ -873,6 +881,11 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
   HIPCHK(hipSetDevice(g->device));
   const bool adapt = beta_growth > 1.0;
   constexpr int kMaxRejects = 40;
+  constexpr double kBetaMax = 1e30;  // a penalty stays representable in FP32
+  // A chunk counts as a rise of the merit only beyond the rounding jitter of
+  // the state it is evaluated on: FP32 states move by a few ulps per sweep
+  // even at a fixed point, which shifts the merit by ~1e-9 relative.
+  const double mtol = g->opt.precision == PGO_FP32 ? 1e-7 : 1e-12;
   std::vector<int32_t> active(size_t(G), 1), done(size_t(G), 0), conv(size_t(G), 0),
       rejects(size_t(G), 0), flags(size_t(G), 0);
   std::vector<double> r, r_acc;
@@ -891,7 +904,7 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
     if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta, active.data())) !=
         PGO_OK)
       return s;
-    if ((s = reduce(g, r)) != PGO_OK) return s;
+    if ((s = reduce(g, r, true)) != PGO_OK) return s;
     bool any_restore = false;
     for (int32_t j = 0; j < G; ++j) {
       flags[size_t(j)] = 0;
@@ -901,10 +914,16 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
         continue;
       }
       const double* v = &r[size_t(kRedVals) * j];
+      const bool finite = finite_graph(r, j);
       double L1, psi1, L0, psi0;
       merit_of(v, beta[j], gamma, &L1, &psi1);
       merit_of(&r_acc[size_t(kRedVals) * j], beta[j], gamma, &L0, &psi0);
-      if (adapt && psi1 > psi0 + 1e-12 * std::fabs(psi0) && rejects[size_t(j)] < kMaxRejects) {
+      const bool rose = !finite || psi1 > psi0 + mtol * std::fabs(psi0);
+      const bool can_raise = rejects[size_t(j)] < kMaxRejects && beta[j] * beta_growth <= kBetaMax;
+      if (!finite && !(adapt && can_raise))
+        return fail(PGO_ENUMERIC, "graph " + std::to_string(j) +
+                                      " reached a non-finite state (penalty too small)");
+      if (adapt && rose && can_raise) {
         flags[size_t(j)] = 1;  // undo this graph's chunk and raise its penalty
         any_restore = true;
         beta[j] *= beta_growth;
@@ -1088,11 +1107,11 @@ pgo_status pgo_set_edge_params(pgo_graph* g, const double* kappa, const double* 
   if (tm && (s = check_device_values(g, tm, 3 * m, false, "tm")) != PGO_OK) return s;
   if (omega && (s = check_device_values(g, omega, 3 * m, false, "omega")) != PGO_OK) return s;
   if (m == 0) return PGO_OK;
-  if (kappa) HIPCHK(hipMemcpyAsync(g->kappa, kappa, 8 * m, hipMemcpyDeviceToDevice, g->stream));
-  if (tau) HIPCHK(hipMemcpyAsync(g->tau, tau, 8 * m, hipMemcpyDeviceToDevice, g->stream));
-  if (tm) HIPCHK(hipMemcpyAsync(g->tm, tm, 24 * m, hipMemcpyDeviceToDevice, g->stream));
+  if (kappa) HIPCHK(launch_copy(g->kappa, kappa, 8 * m, g->stream));
+  if (tau) HIPCHK(launch_copy(g->tau, tau, 8 * m, g->stream));
+  if (tm) HIPCHK(launch_copy(g->tm, tm, 24 * m, g->stream));
   if (omega) {
-    HIPCHK(hipMemcpyAsync(g->omega, omega, 24 * m, hipMemcpyDeviceToDevice, g->stream));
+    HIPCHK(launch_copy(g->omega, omega, 24 * m, g->stream));
     HIPCHK(launch_perturb(g->m, g->qe0, g->omega, g->qe, g->stream));
   }
   s = g->opt.precision == PGO_FP64 ? refill_edges<double>(g) : refill_edges<float>(g);

@@ -77,6 +77,8 @@ hipError_t launch_restore(const DevGraph<T>& g, const Q4<T>* p, const Q4<T>* q, 
 
 // Boundary preparation (prep.hip), FP64.
 // bad[i] = 1 where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
+// device-to-device copy as a kernel (8-byte aligned, size a multiple of 8)
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 hipError_t launch_rot_to_quat(const double* R, int64_t count, Q4<double>* out, int canonical,
                               uint8_t* bad, hipStream_t st);
 hipError_t launch_align(const Q4<double>* pv, Q4<double>* qe, const int32_t* ei,

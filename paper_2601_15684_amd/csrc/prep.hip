@@ -14,68 +14,14 @@
 //  * the state starts at q = p^0, s = t^0, lambda = z = 0.
 #include <hipcub/hipcub.hpp>
 
+#include <algorithm>
+
 #include "internal.hpp"
+#include "polar.hpp"
 
 namespace pgo {
 
 namespace {
-
-__device__ inline double det3(const double r[9]) {
-  return r[0] * (r[4] * r[8] - r[5] * r[7]) - r[1] * (r[3] * r[8] - r[5] * r[6]) +
-         r[2] * (r[3] * r[7] - r[4] * r[6]);
-}
-
-// Polar factor of a 3x3 matrix (row-major in, row-major out) by one-sided
-// Jacobi: right-multiply by plane rotations until the columns are
-// orthogonal, A V = U S, then R = U V^T.  If the result is a reflection the
-// column of U with the smallest singular value changes sign.
-__device__ void polar3(const double a_in[9], double R[9]) {
-  double c[3][3], v[3][3];  // c[k] = column k of A V, v[k] = column k of V
-  for (int k = 0; k < 3; ++k)
-    for (int r = 0; r < 3; ++r) {
-      c[k][r] = a_in[3 * r + k];
-      v[k][r] = (k == r) ? 1.0 : 0.0;
-    }
-  const int P[3] = {0, 0, 1}, Qc[3] = {1, 2, 2};
-  for (int sweep = 0; sweep < 20; ++sweep) {
-    double off = 0.0;
-    for (int pr = 0; pr < 3; ++pr) {
-      const int p = P[pr], q = Qc[pr];
-      const double al = c[p][0] * c[p][0] + c[p][1] * c[p][1] + c[p][2] * c[p][2];
-      const double be = c[q][0] * c[q][0] + c[q][1] * c[q][1] + c[q][2] * c[q][2];
-      const double ga = c[p][0] * c[q][0] + c[p][1] * c[q][1] + c[p][2] * c[q][2];
-      const double scale = sqrt(al * be);
-      if (scale == 0.0 || fabs(ga) <= 1e-17 * scale) continue;
-      off = fmax(off, fabs(ga) / scale);
-      const double zeta = (be - al) / (2.0 * ga);
-      const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-      for (int r = 0; r < 3; ++r) {
-        const double cp = c[p][r], cq = c[q][r];
-        c[p][r] = cs * cp - sn * cq;
-        c[q][r] = sn * cp + cs * cq;
-        const double vp = v[p][r], vq = v[q][r];
-        v[p][r] = cs * vp - sn * vq;
-        v[q][r] = sn * vp + cs * vq;
-      }
-    }
-    if (off < 1e-16) break;
-  }
-  double sig[3];
-  for (int k = 0; k < 3; ++k) {
-    sig[k] = sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]);
-    const double inv = sig[k] > 0.0 ? 1.0 / sig[k] : 0.0;
-    for (int r = 0; r < 3; ++r) c[k][r] *= inv;
-  }
-  for (int pass = 0; pass < 2; ++pass) {
-    for (int r = 0; r < 3; ++r)
-      for (int s = 0; s < 3; ++s)
-        R[3 * r + s] = c[0][r] * v[0][s] + c[1][r] * v[1][s] + c[2][r] * v[2][s];
-    if (det3(R) > 0.0) break;
-    const int kmin = (sig[0] <= sig[1] && sig[0] <= sig[2]) ? 0 : (sig[1] <= sig[2] ? 1 : 2);
-    for (int r = 0; r < 3; ++r) c[kmin][r] = -c[kmin][r];
-  }
-}
 
 __device__ Q4<double> quat_of_rot(const double r[9]) {
   const double tr = r[0] + r[4] + r[8];
@@ -111,14 +57,14 @@ __global__ void k_rot_to_quat(const double* __restrict__ R, int64_t count,
       const double d = a[r] * a[s] + a[3 + r] * a[3 + s] + a[6 + r] * a[6 + s] - (r == s ? 1.0 : 0.0);
       dev += d * d;
     }
-  const bool ok = det3(a) > 0.0 && sqrt(dev) <= 1e-2;
+  const bool ok = det3<double>(a) > 0.0 && sqrt(dev) <= 1e-2;
   bad[i] = ok ? 0 : 1;
   if (!ok) {
     out[i] = Q4<double>{1.0, 0.0, 0.0, 0.0};
     return;
   }
-  double rot[9];
-  polar3(a, rot);
+  double rot[9], sig[3];
+  polar3<double>(a, rot, sig);
   Q4<double> q = quat_of_rot(rot);
   if (canonical) {
     const double lead = fabs(q.w) > 1e-6 ? q.w : fabs(q.x) > 1e-6 ? q.x : fabs(q.y) > 1e-6 ? q.y : q.z;
@@ -368,5 +314,26 @@ hipError_t launch_poses(const DevGraph<T>& g, double* R, double* t, hipStream_t 
 PGO_INST(float)
 PGO_INST(double)
 #undef PGO_INST
+
+// Device-to-device copy of 8-byte words as an ordinary kernel on the stream,
+// so it is ordered with the sweep launches (plain or replayed graphs) exactly
+// like every other kernel of the library.
+__global__ void k_copy_words(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src,
+                             int64_t words) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += stride)
+    dst[k] = src[k];
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return hipSuccess;
+  if (bytes % 8 || reinterpret_cast<uintptr_t>(dst) % 8 || reinterpret_cast<uintptr_t>(src) % 8)
+    return hipErrorInvalidValue;
+  const int64_t words = int64_t(bytes / 8);
+  const int64_t blocks = std::min<int64_t>((words + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_copy_words, dim3(unsigned(blocks)), dim3(256), 0, st,
+                     static_cast<uint64_t*>(dst), static_cast<const uint64_t*>(src), words);
+  return hipGetLastError();
+}
 
 }  // namespace pgo

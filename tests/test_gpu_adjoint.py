@@ -27,13 +27,13 @@ def cuda(x):
     return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda")
 
 
-def gpu_grads(pgo, g, K, beta, C, prec, omega=None):
+def gpu_grads(pgo, g, K, beta, C, prec, omega=None, schedule="auto"):
     from paper_2601_15684_amd.autograd import unrolled_pradmm
     kappa = cuda(g.kappa).requires_grad_()
     tau = cuda(g.tau).requires_grad_()
     tm = cuda(g.tm).requires_grad_()
     om = cuda(np.zeros((g.m, 3)) if omega is None else omega).requires_grad_()
-    with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+    with pgo.PoseGraph.from_graph(g, precision=prec, schedule=schedule) as h:
         state = unrolled_pradmm(h, kappa, tau, tm, om, K, beta, GAMMA, C)
         loss = ((state[:, 8:11] - cuda(g.t_gt)) ** 2).sum()
         loss.backward()
@@ -46,17 +46,32 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
+@pytest.mark.parametrize("sched", ["phase", "graph"])
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-8), ("fp32", 1e-3)])
 @pytest.mark.parametrize("K,C", [(10, 3), (6, 6)])
-def test_adjoint_matches_oracle(pgo, prec, tol, K, C):
+def test_adjoint_matches_oracle(pgo, prec, tol, K, C, sched):
     g = S.grid(4, 3, 3, all_pairs=True, sigma_R=0.05, sigma_t=0.1, seed=0)
     beta = 0.05 * abar(g)
     P, p0, t0 = prep.prepare_graph(g)
     L_ref, ref = O.unrolled_grad(P, p0, t0, K, beta, GAMMA, torch.as_tensor(g.t_gt))
-    L, got = gpu_grads(pgo, g, K, beta, C, prec)
+    L, got = gpu_grads(pgo, g, K, beta, C, prec, schedule=sched)
     assert abs(L - L_ref) <= (1e-10 if prec == "fp64" else 1e-4) * L_ref
     for k in ("kappa", "tau", "tm", "omega"):
         assert rel(got[k], ref[k].numpy()) <= tol, (k, rel(got[k], ref[k].numpy()))
+
+
+@pytest.mark.parametrize("sched,C", [("phase", 10), ("phase", 50), ("graph", 10)])
+def test_adjoint_fp32_matches_fp64_grid_1k(pgo, sched, C):
+    """K = 50 sweeps of the 1000-pose grid: the FP32 adjoint against the FP64
+    one in each schedule, with several checkpoint segments (C = 10) and one
+    (C = 50).  A float32 run of the oracle's own automatic differentiation
+    departs from its float64 run by ~5e-6 here."""
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    _, g64 = gpu_grads(pgo, g, 50, beta, C, "fp64", schedule=sched)
+    _, g32 = gpu_grads(pgo, g, 50, beta, C, "fp32", schedule=sched)
+    errs = {k: rel(g32[k], g64[k]) for k in g64}
+    assert max(errs.values()) <= 1e-4, errs
 
 
 def test_adjoint_state_gradient_matches_oracle(pgo):
@@ -75,6 +90,7 @@ def test_adjoint_state_gradient_matches_oracle(pgo):
     with pgo.PoseGraph.from_graph(g) as h:
         pgo.pgo_forward_record(h.h, K, beta, GAMMA, 3)
         wd = cuda(w.numpy())
+        torch.cuda.synchronize()  # the library runs on the handle's own stream
         d0 = torch.empty((g.n, 21), dtype=torch.float64, device="cuda")
         pgo.pgo_adjoint(h.h, wd.data_ptr(), 0, 0, 0, 0, d0.data_ptr())
         torch.cuda.synchronize()
@@ -83,6 +99,7 @@ def test_adjoint_state_gradient_matches_oracle(pgo):
 
 
 def _fd_t(pgo, h, base, K, beta, C):
+    torch.cuda.synchronize()  # parameters written by torch, read on the handle's own stream
     pgo.pgo_set_edge_params(h.h, base["kappa"].data_ptr(), base["tau"].data_ptr(),
                             base["tm"].data_ptr(), base["omega"].data_ptr())
     pgo.pgo_reset_state(h.h)
@@ -159,6 +176,7 @@ def test_adjoint_requires_a_recorded_pass(pgo):
         assert ex.value.name == "PGO_ESTATE"
         bad = cuda(g.kappa)
         bad[3] = -1.0
+        torch.cuda.synchronize()
         with pytest.raises(pgo.PgoError) as ex:
             pgo.pgo_set_edge_params(h.h, bad.data_ptr(), 0, 0, 0)
         assert ex.value.name == "PGO_EINVAL" and "kappa entry 3" in str(ex.value)
