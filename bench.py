@@ -268,7 +268,11 @@ def main():
     algo_bytes = (B_EDGE * m + B_VERTEX * n) * args.sweeps
     achieved = algo_bytes / (r32["kern_ms"] * 1e-3) / 1e9
     phase_bytes = (B_EDGE_PHASE * m + B_VERTEX_PHASE * n) * args.sweeps
-    kname = "k_graph_sweeps<float>" if r32["info"]["schedule"] == 2 else "k_phase<*,float>"
+    # the per-graph kernel keeps lambda and z in LDS when 32 B x the largest
+    # graph's pose count fits in 160 KiB (FP32)
+    max_n = int(np.max(voff[1:] - voff[:-1]))
+    kname = (("k_graph_sweeps_lds<float>" if 32 * max_n <= 160 * 1024 else "k_graph_sweeps<float>")
+             if r32["info"]["schedule"] == 2 else "k_phase<*,float>")
     F0, F1 = r32["F0"], r32["res"][:, 5]
     out = {
         "metric": "edge-iters/s + time to 1e-6 rel cost; FP32/batched vs plain FP64, 1 GPU",

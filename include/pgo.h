@@ -17,6 +17,15 @@
  *     beta = beta1 = beta2; proximal weights H_s = h_s I.
  *   - state of a vertex, as 21 doubles: p(4) q(4) t(3) s(3) lambda(4) z(3).
  *
+ * Second model (pgo_options.model = PGO_MODEL_CHORDAL): the same splitting
+ * and sweep applied to the chordal cost (chordal distance of App. A.4 on the
+ * rotation measurements, model (1)'s translation term), rotations kept as
+ * 3x3 matrices: P_i in SO(3) (a 3x3 polar factor per vertex and sweep),
+ * Q_i and the multiplier Lambda_i free 3x3 blocks.  This is not the paper's
+ * quaternion model; its state is 36 doubles per vertex:
+ * P(9) Q(9) t(3) s(3) Lambda(9) z(3), matrices row-major.  Everything below
+ * applies to both models unless it says otherwise.
+ *
  * Ownership: host arrays passed to pgo_create* are read during the call and
  * copied; the caller keeps them.  A handle owns all of its device memory
  * until pgo_destroy.  Output buffers are caller-allocated.  Pointers named
@@ -67,6 +76,14 @@ typedef enum {
 
 #define PGO_GRAPH_SCHED_MAX_N 65536
 
+typedef enum {
+  PGO_MODEL_QUAT = 0,    /* the paper's unit-quaternion model (eq. 1-2) */
+  PGO_MODEL_CHORDAL = 1  /* rotation matrices, chordal rotation cost; FP32
+                            takes the P update's 3x3 polar factor in double
+                            when it is ill-conditioned (sigma_2 + sign(det)
+                            sigma_3 below 1e-2 of the summed term sizes) */
+} pgo_model;
+
 typedef struct {
   double h1, h2, h3, h4; /* proximal weights H_1..H_4 (defaults 1, 1e-3, 1e-3,
                             1e-3: the experiment settings) */
@@ -74,6 +91,7 @@ typedef struct {
   int32_t schedule;      /* pgo_schedule, default PGO_SCHED_AUTO */
   int32_t block;         /* threads per workgroup; 0 = library default */
   int32_t device;        /* HIP device ordinal, default 0 */
+  int32_t model;         /* pgo_model, default PGO_MODEL_QUAT */
 } pgo_options;
 
 /* Fill *opt with the defaults above. */
@@ -192,22 +210,25 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
                      double tol, double beta_growth, double* beta, int32_t* sweeps_done,
                      int32_t* converged);
 
-/* Current poses: R(p_i) (n x 9, row-major) and t_i (n x 3); either may be NULL. */
+/* Current poses: R(p_i) (chordal model: P_i) (n x 9, row-major) and t_i
+ * (n x 3); either may be NULL. */
 pgo_status pgo_get_poses(pgo_graph* g, double* R, double* t);
 
-/* Raw state, n x 21 doubles (see conventions); set_state restarts the
- * residual history (the next residuals report d = 0 until a sweep runs). */
+/* Raw state, n x 21 doubles (chordal model: n x 36; see conventions);
+ * set_state restarts the residual history (the next residuals report d = 0
+ * until a sweep runs). */
 pgo_status pgo_get_state(pgo_graph* g, double* state);
 pgo_status pgo_set_state(pgo_graph* g, const double* state);
 
 /* The prepared (projected, converted, sign-aligned) edge quaternions in the
  * caller's edge order (m x 4) and vertex quaternions p^0 (n x 4); either may
- * be NULL. */
+ * be NULL.  Chordal model: the projected measured rotations (m x 9) and
+ * initial rotations P^0 (n x 9), row-major. */
 pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat0);
 
-/* Sizes of the handle; any pointer may be NULL. */
+/* Sizes and settings of the handle; any pointer may be NULL. */
 pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
-                    int32_t* schedule, int32_t* block);
+                    int32_t* schedule, int32_t* block, int32_t* model);
 
 /*
  * pgo_autotune -- time the candidate schedules and workgroup sizes on this
@@ -219,6 +240,8 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
 
 /*
  * Differentiation of K unrolled sweeps (reverse mode written by hand).
+ * pgo_set_edge_params, pgo_forward_record and pgo_adjoint exist for the
+ * quaternion model only (PGO_ESTATE on a chordal handle).
  *
  * pgo_set_edge_params -- replace edge parameters in place (caller edge
  * order, device FP64 pointers; NULL keeps the current values): kappa (m),
@@ -233,10 +256,11 @@ pgo_status pgo_set_edge_params(pgo_graph* g, const double* kappa_dev, const doub
                                const double* tm_dev, const double* omega_dev);
 
 /* Put the state back to the initial point of pgo_create (q = p^0, s = t^0,
- * lambda = z = 0). */
+ * lambda = z = 0; chordal: Q = P^0, Lambda = 0). */
 pgo_status pgo_reset_state(pgo_graph* g);
 
-/* The state as n x 21 doubles written to a device buffer (asynchronous). */
+/* The state (n x 21, chordal n x 36 doubles) written to a device buffer
+ * (asynchronous). */
 pgo_status pgo_get_state_dev(pgo_graph* g, double* state_dev);
 
 /*

@@ -19,12 +19,15 @@ __all__ = [
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
     "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint",
-    "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "LIB_PATH",
+    "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "MODEL_QUAT", "MODEL_CHORDAL",
+    "LIB_PATH", "split_state",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpgo.so")
 FP64, FP32 = 0, 1
 SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH = 0, 1, 2
+MODEL_QUAT, MODEL_CHORDAL = 0, 1
+STATE_WIDTH = {MODEL_QUAT: 21, MODEL_CHORDAL: 36}
 STATUS = {0: "PGO_OK", 1: "PGO_EINVAL", 2: "PGO_ENOMEM", 3: "PGO_EDEVICE", 4: "PGO_ENUMERIC",
           5: "PGO_ESTATE"}
 
@@ -39,7 +42,7 @@ class PgoError(RuntimeError):
 class PgoOptions(C.Structure):
     _fields_ = [("h1", C.c_double), ("h2", C.c_double), ("h3", C.c_double), ("h4", C.c_double),
                 ("precision", C.c_int32), ("schedule", C.c_int32), ("block", C.c_int32),
-                ("device", C.c_int32)]
+                ("device", C.c_int32), ("model", C.c_int32)]
 
 
 _P = C.c_void_p
@@ -66,7 +69,7 @@ _SIGNATURES = {
     "pgo_get_state": (C.c_int, [_P, _D]),
     "pgo_set_state": (C.c_int, [_P, _D]),
     "pgo_get_prepared": (C.c_int, [_P, _D, _D]),
-    "pgo_info": (C.c_int, [_P, _I64, _I64, _I32, _I32, _I32, _I32]),
+    "pgo_info": (C.c_int, [_P, _I64, _I64, _I32, _I32, _I32, _I32, _I32]),
     "pgo_autotune": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32]),
     "pgo_set_edge_params": (C.c_int, [_P, _P, _P, _P, _P]),
     "pgo_reset_state": (C.c_int, [_P]),
@@ -132,6 +135,8 @@ def pgo_default_options(**kw) -> PgoOptions:
             o.precision = {"fp64": FP64, "fp32": FP32}[v]
         elif k == "schedule" and isinstance(v, str):
             o.schedule = {"auto": SCHED_AUTO, "phase": SCHED_PHASE, "graph": SCHED_GRAPH}[v]
+        elif k == "model" and isinstance(v, str):
+            o.model = {"quat": MODEL_QUAT, "chordal": MODEL_CHORDAL}[v]
         else:
             setattr(o, k, v)
     return o
@@ -178,11 +183,11 @@ def pgo_iterate_graphs(h, k, beta, gamma):
 
 def pgo_info(h):
     n, m = C.c_int64(), C.c_int64()
-    G, prec, sched, block = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    G, prec, sched, block, model = (C.c_int32() for _ in range(5))
     _chk(lib().pgo_info(h, C.byref(n), C.byref(m), C.byref(G), C.byref(prec), C.byref(sched),
-                        C.byref(block)))
+                        C.byref(block), C.byref(model)))
     return dict(n=n.value, m=m.value, G=G.value, precision=prec.value, schedule=sched.value,
-                block=block.value)
+                block=block.value, model=model.value, width=STATE_WIDTH[model.value])
 
 
 def pgo_cost(h):
@@ -223,22 +228,24 @@ def pgo_get_poses(h):
 
 
 def pgo_get_state(h):
-    n = pgo_info(h)["n"]
-    out = np.empty((n, 21), np.float64)
+    info = pgo_info(h)
+    out = np.empty((info["n"], info["width"]), np.float64)
     _chk(lib().pgo_get_state(h, _dp(out)))
     return out
 
 
 def pgo_set_state(h, state):
     info = pgo_info(h)
-    s = _f64(state, (info["n"], 21))
+    s = _f64(state, (info["n"], info["width"]))
     _chk(lib().pgo_set_state(h, _dp(s)))
 
 
 def pgo_get_prepared(h):
+    """Quaternion model: (m x 4, n x 4) quaternions; chordal: (m x 3 x 3, n x 3 x 3)."""
     info = pgo_info(h)
-    qe = np.empty((info["m"], 4), np.float64)
-    p0 = np.empty((info["n"], 4), np.float64)
+    shape = (4,) if info["model"] == MODEL_QUAT else (3, 3)
+    qe = np.empty((info["m"],) + shape, np.float64)
+    p0 = np.empty((info["n"],) + shape, np.float64)
     _chk(lib().pgo_get_prepared(h, _dp(qe), _dp(p0)))
     return qe, p0
 
@@ -280,8 +287,13 @@ def pgo_destroy(h):
 
 
 def split_state(state):
-    """(n,21) state -> dict p, q, t, s, lam, z."""
+    """(n,21) state -> dict p, q, t, s, lam, z; (n,36) chordal state ->
+    dict P, Q (n,3,3), t, s, L (n,3,3), z."""
     s = np.asarray(state)
+    if s.shape[1] == 36:
+        n = s.shape[0]
+        return dict(P=s[:, 0:9].reshape(n, 3, 3), Q=s[:, 9:18].reshape(n, 3, 3), t=s[:, 18:21],
+                    s=s[:, 21:24], L=s[:, 24:33].reshape(n, 3, 3), z=s[:, 33:36])
     return dict(p=s[:, 0:4], q=s[:, 4:8], t=s[:, 8:11], s=s[:, 11:14], lam=s[:, 14:18], z=s[:, 18:21])
 
 

@@ -1,7 +1,8 @@
 // Host side of the C ABI declared in include/pgo.h: argument checking,
 // device memory ownership, the boundary preparation sequence, schedule
 // selection, the autotuner and the host<->device transfers.  All arithmetic
-// of the method runs in the kernels of sweep.hip, prep.hip and reduce.hip.
+// of the method runs in the kernels of sweep.hip (quaternion model),
+// chordal.hip (rotation-matrix model), prep.hip, reduce.hip and adjoint.hip.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,6 +46,7 @@ struct pgo_graph {
   hipStream_t own_stream = nullptr;
   hipStream_t stream = nullptr;
   pgo_options opt{};
+  bool chordal = false;             // PGO_MODEL_CHORDAL
   int64_t n = 0, m = 0;
   int32_t G = 0;
   int32_t max_n = 0;
@@ -81,11 +83,13 @@ struct pgo_graph {
   Q4<double>* qe = nullptr;
   double *tm = nullptr, *kappa = nullptr, *tau = nullptr;
   Q4<double>* p0 = nullptr;
+  double* R9 = nullptr;             // chordal: projected measured rotations, caller order (m x 9)
+  double* P0 = nullptr;             // chordal: projected initial rotations (n x 9)
   int n_ech = 0, n_vch = 0;
   int64_t *ec_beg = nullptr, *ec_end = nullptr, *vc_beg = nullptr, *vc_end = nullptr;
   int32_t *g_ec_off = nullptr, *g_vc_off = nullptr;
   double *part_e = nullptr, *part_v = nullptr, *red_out = nullptr;
-  double* iobuf = nullptr;  // n x 21 doubles, allocated on first use
+  double* iobuf = nullptr;  // n x state width doubles, allocated on first use
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
@@ -164,6 +168,40 @@ DevGraph<T> view(const pgo_graph* g) {
   return d;
 }
 
+template <typename T>
+DevChordal<T> viewc(const pgo_graph* g) {
+  DevChordal<T> d;
+  d.n = int32_t(g->n);
+  d.gid = g->gid;
+  d.o_ptr = g->o_ptr;
+  d.o_nbr = g->o_nbr;
+  d.o_tt = static_cast<const P4<T>*>(g->o_tt);
+  d.o_R = static_cast<const R3<T>*>(g->o_w);
+  d.i_ptr = g->i_ptr;
+  d.i_nbr = g->i_nbr;
+  d.i_tt = static_cast<const P4<T>*>(g->i_tt);
+  d.i_R = static_cast<const R3<T>*>(g->i_w);
+  d.cQ = static_cast<const T*>(g->cQ);
+  d.cT = static_cast<const T*>(g->cT);
+  d.cS = static_cast<const T*>(g->cS);
+  d.P = static_cast<R3<T>*>(g->p);
+  d.Q = static_cast<R3<T>*>(g->q);
+  d.L = static_cast<R3<T>*>(g->lam);
+  d.t = static_cast<P4<T>*>(g->t);
+  d.s = static_cast<P4<T>*>(g->s);
+  d.z = static_cast<P4<T>*>(g->z);
+  d.Q_prev = static_cast<R3<T>*>(g->q_prev);
+  d.L_prev = static_cast<R3<T>*>(g->lam_prev);
+  d.t_prev = static_cast<P4<T>*>(g->t_prev);
+  d.s_prev = static_cast<P4<T>*>(g->s_prev);
+  d.z_prev = static_cast<P4<T>*>(g->z_prev);
+  return d;
+}
+
+// words of T per vertex of a rotation-like block (p, q, lambda and edge w)
+int rot_words(const pgo_graph* g) { return g->chordal ? 12 : 4; }
+int state_width(const pgo_graph* g) { return g->chordal ? 36 : 21; }
+
 bool finite_all(const double* a, size_t k) {
   for (size_t i = 0; i < k; ++i)
     if (!std::isfinite(a[i])) return false;
@@ -181,6 +219,8 @@ pgo_status check_options(const pgo_options& o) {
     return fail(PGO_EINVAL, "unknown schedule");
   if (o.block != 0 && (o.block < 64 || o.block > 1024 || o.block % 64 != 0))
     return fail(PGO_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
+  if (o.model != PGO_MODEL_QUAT && o.model != PGO_MODEL_CHORDAL)
+    return fail(PGO_EINVAL, "model must be PGO_MODEL_QUAT or PGO_MODEL_CHORDAL");
   return PGO_OK;
 }
 
@@ -252,15 +292,20 @@ pgo_status build_chunks(pgo_graph* g) {
 
 template <typename T>
 pgo_status alloc_precision(pgo_graph* g) {
-  const size_t n = size_t(g->n), m = size_t(g->m);
+  const size_t n = size_t(g->n), m = size_t(g->m), rw = size_t(rot_words(g));
   pgo_status s;
-  void** vec4[] = {&g->p, &g->q, &g->lam, &g->t, &g->s, &g->z,
-                   &g->q_prev, &g->lam_prev, &g->t_prev, &g->s_prev, &g->z_prev};
+  void** rot[] = {&g->p, &g->q, &g->lam, &g->q_prev, &g->lam_prev};
+  for (void** v : rot)
+    if ((s = dalloc_bytes(g, v, rw * sizeof(T) * n)) != PGO_OK) return s;
+  void** vec4[] = {&g->t, &g->s, &g->z, &g->t_prev, &g->s_prev, &g->z_prev};
   for (void** v : vec4)
     if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * n)) != PGO_OK) return s;
-  void** e4[] = {&g->o_tt, &g->o_w, &g->i_tt, &g->i_w};
+  void** e4[] = {&g->o_tt, &g->i_tt};
   for (void** v : e4)
     if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * m)) != PGO_OK) return s;
+  void** ew[] = {&g->o_w, &g->i_w};
+  for (void** v : ew)
+    if ((s = dalloc_bytes(g, v, rw * sizeof(T) * m)) != PGO_OK) return s;
   void** c1[] = {&g->cQ, &g->cT, &g->cS};
   for (void** v : c1)
     if ((s = dalloc_bytes(g, v, sizeof(T) * n)) != PGO_OK) return s;
@@ -270,6 +315,17 @@ pgo_status alloc_precision(pgo_graph* g) {
 template <typename T>
 pgo_status prepare_precision(pgo_graph* g, const double* t0_dev) {
   hipStream_t st = g->stream;
+  if (g->chordal) {
+    HIPCHK(launch_fill_edges_c<T>(g->o_perm, g->ej, g->R9, g->tm, g->kappa, g->tau, g->m, g->o_nbr,
+                                  static_cast<P4<T>*>(g->o_tt), static_cast<R3<T>*>(g->o_w), st));
+    HIPCHK(launch_fill_edges_c<T>(g->i_perm, g->ei, g->R9, g->tm, g->kappa, g->tau, g->m, g->i_nbr,
+                                  static_cast<P4<T>*>(g->i_tt), static_cast<R3<T>*>(g->i_w), st));
+    HIPCHK(launch_vertex_consts_c<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm,
+                                     g->kappa, g->tau, static_cast<T*>(g->cQ),
+                                     static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
+    HIPCHK(launch_init_state_c<T>(viewc<T>(g), g->P0, t0_dev, st));
+    return PGO_OK;
+  }
   HIPCHK(launch_fill_edges<T>(g->o_perm, g->ej, g->qe, g->tm, g->kappa, g->tau, g->m, g->o_nbr,
                               static_cast<P4<T>*>(g->o_tt), static_cast<Q4<T>*>(g->o_w), st));
   HIPCHK(launch_fill_edges<T>(g->i_perm, g->ei, g->qe, g->tm, g->kappa, g->tau, g->m, g->i_nbr,
@@ -358,6 +414,7 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   pgo_graph* g = new pgo_graph();
   g->device = opt.device;
   g->opt = opt;
+  g->chordal = opt.model == PGO_MODEL_CHORDAL;
   g->G = G;
   g->n = voff[G];
   g->m = eoff[G];
@@ -409,34 +466,52 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   if ((s = dalloc(g, &g->active_dev, size_t(G))) != PGO_OK) return bail(s);
   if ((s = dalloc(g, &g->flag_dev, size_t(G))) != PGO_OK) return bail(s);
   g->beta_h.assign(size_t(G), 1.0);
-  if ((s = dalloc(g, &g->p0, size_t(n))) != PGO_OK) return bail(s);
-  if ((s = dalloc(g, &g->qe, size_t(m))) != PGO_OK) return bail(s);
   if ((s = dalloc(g, &bad, size_t(std::max(n, m)))) != PGO_OK) return bail(s);
-
-  // rotations -> quaternions (with validity flags)
-  he = launch_rot_to_quat(R0d, n, g->p0, 1, bad, g->stream);
-  if (he != hipSuccess) return bail(hip_fail(he, "rot_to_quat"));
   int64_t badi = -1;
-  if ((s = first_bad(g, bad, n, &badi)) != PGO_OK) return bail(s);
-  if (badi >= 0)
-    return bail(fail(PGO_EINVAL, "initial rotation " + std::to_string(badi) +
-                                     " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
-  he = launch_rot_to_quat(Rmd, m, g->qe, 0, bad, g->stream);
-  if (he != hipSuccess) return bail(hip_fail(he, "rot_to_quat"));
-  if ((s = first_bad(g, bad, m, &badi)) != PGO_OK) return bail(s);
-  if (badi >= 0)
-    return bail(fail(PGO_EINVAL, "measured rotation of edge " + std::to_string(badi) +
-                                     " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
-  he = launch_align(g->p0, g->qe, g->ei, g->ej, m, g->stream);
-  if (he != hipSuccess) return bail(hip_fail(he, "align"));
-  if ((s = dalloc(g, &g->qe0, size_t(m))) != PGO_OK) return bail(s);
-  if (m) {
-    he = launch_copy(g->qe0, g->qe, sizeof(Q4<double>) * size_t(m), g->stream);
-    if (he != hipSuccess) return bail(hip_fail(he, "copy"));
-  }
-  {
-    std::vector<double> zeros(size_t(3 * m), 0.0);
-    if ((s = upload(g, &g->omega, zeros.data(), zeros.size())) != PGO_OK) return bail(s);
+  if (g->chordal) {
+    // rotations projected onto SO(3) (with validity flags)
+    if ((s = dalloc(g, &g->P0, size_t(9 * n))) != PGO_OK) return bail(s);
+    if ((s = dalloc(g, &g->R9, size_t(9 * m))) != PGO_OK) return bail(s);
+    he = launch_project_rot(R0d, n, g->P0, bad, g->stream);
+    if (he != hipSuccess) return bail(hip_fail(he, "project_rot"));
+    if ((s = first_bad(g, bad, n, &badi)) != PGO_OK) return bail(s);
+    if (badi >= 0)
+      return bail(fail(PGO_EINVAL, "initial rotation " + std::to_string(badi) +
+                                       " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
+    he = launch_project_rot(Rmd, m, g->R9, bad, g->stream);
+    if (he != hipSuccess) return bail(hip_fail(he, "project_rot"));
+    if ((s = first_bad(g, bad, m, &badi)) != PGO_OK) return bail(s);
+    if (badi >= 0)
+      return bail(fail(PGO_EINVAL, "measured rotation of edge " + std::to_string(badi) +
+                                       " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
+  } else {
+    if ((s = dalloc(g, &g->p0, size_t(n))) != PGO_OK) return bail(s);
+    if ((s = dalloc(g, &g->qe, size_t(m))) != PGO_OK) return bail(s);
+
+    // rotations -> quaternions (with validity flags)
+    he = launch_rot_to_quat(R0d, n, g->p0, 1, bad, g->stream);
+    if (he != hipSuccess) return bail(hip_fail(he, "rot_to_quat"));
+    if ((s = first_bad(g, bad, n, &badi)) != PGO_OK) return bail(s);
+    if (badi >= 0)
+      return bail(fail(PGO_EINVAL, "initial rotation " + std::to_string(badi) +
+                                       " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
+    he = launch_rot_to_quat(Rmd, m, g->qe, 0, bad, g->stream);
+    if (he != hipSuccess) return bail(hip_fail(he, "rot_to_quat"));
+    if ((s = first_bad(g, bad, m, &badi)) != PGO_OK) return bail(s);
+    if (badi >= 0)
+      return bail(fail(PGO_EINVAL, "measured rotation of edge " + std::to_string(badi) +
+                                       " is not a rotation (det <= 0 or ||R^T R - I||_F > 1e-2)"));
+    he = launch_align(g->p0, g->qe, g->ei, g->ej, m, g->stream);
+    if (he != hipSuccess) return bail(hip_fail(he, "align"));
+    if ((s = dalloc(g, &g->qe0, size_t(m))) != PGO_OK) return bail(s);
+    if (m) {
+      he = launch_copy(g->qe0, g->qe, sizeof(Q4<double>) * size_t(m), g->stream);
+      if (he != hipSuccess) return bail(hip_fail(he, "copy"));
+    }
+    {
+      std::vector<double> zeros(size_t(3 * m), 0.0);
+      if ((s = upload(g, &g->omega, zeros.data(), zeros.size())) != PGO_OK) return bail(s);
+    }
   }
   dfree(g, R0d);
   dfree(g, Rmd);
@@ -484,14 +559,22 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
   SweepParams sp{beta, gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4,
                  per_graph ? g->beta_dev : nullptr, masked ? g->active_dev : nullptr};
   const DevGraph<T> d = view<T>(g);
+  const DevChordal<T> dc = viewc<T>(g);
   if (sched == PGO_SCHED_GRAPH) {
-    HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->max_n,
-                                  g->graph_regs, g->stream));
+    if (g->chordal)
+      HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->stream));
+    else
+      HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->max_n,
+                                    g->graph_regs, g->stream));
     return PGO_OK;
   }
+  auto phases = [&](hipStream_t st) {
+    return g->chordal ? launch_phase_sweeps_c<T>(dc, k, sp, block, st)
+                      : launch_phase_sweeps<T>(d, k, sp, block, st);
+  };
   // per-phase launches, captured once into a HIP graph per (k, beta, gamma, block)
   if (k == 1) {
-    HIPCHK(launch_phase_sweeps<T>(d, k, sp, block, g->stream));
+    HIPCHK(phases(g->stream));
     return PGO_OK;
   }
   if (!(g->gexec && g->g_k == k && g->g_beta == beta && g->g_gamma == gamma &&
@@ -502,7 +585,7 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
     }
     hipGraph_t graph = nullptr;
     HIPCHK(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal));
-    const hipError_t le = launch_phase_sweeps<T>(d, k, sp, block, g->stream);
+    const hipError_t le = phases(g->stream);
     const hipError_t ce = hipStreamEndCapture(g->stream, &graph);
     if (le != hipSuccess) {
       if (graph) (void)hipGraphDestroy(graph);
@@ -555,9 +638,17 @@ pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int 
 // non-finite value anywhere is reported as PGO_ENUMERIC.
 pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite = false) {
   HIPCHK(hipSetDevice(g->device));
-  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau};
+  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9};
   hipError_t he;
-  if (g->opt.precision == PGO_FP64)
+  if (g->chordal && g->opt.precision == PGO_FP64)
+    he = launch_reduce_c<double>(viewc<double>(g), e, g->have_prev, g->ec_beg, g->ec_end, g->n_ech,
+                                 g->vc_beg, g->vc_end, g->n_vch, g->part_e, g->part_v,
+                                 g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
+  else if (g->chordal)
+    he = launch_reduce_c<float>(viewc<float>(g), e, g->have_prev, g->ec_beg, g->ec_end, g->n_ech,
+                                g->vc_beg, g->vc_end, g->n_vch, g->part_e, g->part_v, g->g_ec_off,
+                                g->g_vc_off, g->G, g->red_out, g->stream);
+  else if (g->opt.precision == PGO_FP64)
     he = launch_reduce<double>(view<double>(g), e, g->have_prev, nullptr, g->ec_beg, g->ec_end,
                                g->n_ech, nullptr, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
                                g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
@@ -584,7 +675,7 @@ bool finite_graph(const std::vector<double>& r, int32_t j) {
 
 pgo_status ensure_iobuf(pgo_graph* g) {
   if (g->iobuf) return PGO_OK;
-  return dalloc(g, &g->iobuf, size_t(21) * g->n);
+  return dalloc(g, &g->iobuf, size_t(state_width(g)) * g->n);
 }
 
 }  // namespace
@@ -599,39 +690,41 @@ void merit_of(const double* v, double beta, double gamma, double* L, double* psi
   *psi = *L + a1 / (gamma * beta) * v[kDL2];
 }
 
-template <typename T>
-pgo_status snapshot_or_restore(pgo_graph* g, bool restore) {
-  const size_t n = size_t(g->n);
-  const size_t bytes = 4 * sizeof(T) * n;
-  void* cur[6] = {g->p, g->q, g->lam, g->t, g->s, g->z};
-  if (!restore) {
-    for (int k = 0; k < 6; ++k) {
-      if (!g->snap[k]) {
-        pgo_status s = dalloc_bytes(g, &g->snap[k], bytes);
-        if (s != PGO_OK) return s;
-      }
-      HIPCHK(launch_copy(g->snap[k], cur[k], bytes, g->stream));
-    }
-    return PGO_OK;
-  }
-  HIPCHK(launch_restore<T>(view<T>(g), static_cast<const Q4<T>*>(g->snap[0]),
-                           static_cast<const Q4<T>*>(g->snap[1]), static_cast<const Q4<T>*>(g->snap[2]),
-                           static_cast<const P4<T>*>(g->snap[3]), static_cast<const P4<T>*>(g->snap[4]),
-                           static_cast<const P4<T>*>(g->snap[5]), g->flag_dev, g->stream));
-  return PGO_OK;
+// bytes per vertex of the six state arrays (p, q, lambda, t, s, z)
+void state_array_bytes(const pgo_graph* g, size_t out[6]) {
+  const size_t w = g->opt.precision == PGO_FP64 ? 8 : 4;
+  for (int k = 0; k < 3; ++k) out[k] = size_t(rot_words(g)) * w;
+  for (int k = 3; k < 6; ++k) out[k] = 4 * w;
 }
 
 pgo_status snapshot(pgo_graph* g) {
-  return g->opt.precision == PGO_FP64 ? snapshot_or_restore<double>(g, false)
-                                      : snapshot_or_restore<float>(g, false);
+  size_t vb[6];
+  state_array_bytes(g, vb);
+  void* cur[6] = {g->p, g->q, g->lam, g->t, g->s, g->z};
+  for (int k = 0; k < 6; ++k) {
+    const size_t bytes = vb[k] * size_t(g->n);
+    if (!g->snap[k]) {
+      pgo_status s = dalloc_bytes(g, &g->snap[k], bytes);
+      if (s != PGO_OK) return s;
+    }
+    HIPCHK(launch_copy(g->snap[k], cur[k], bytes, g->stream));
+  }
+  return PGO_OK;
 }
 
 pgo_status restore_flagged(pgo_graph* g, const std::vector<int32_t>& flags) {
   HIPCHK(hipMemcpyAsync(g->flag_dev, flags.data(), sizeof(int32_t) * g->G, hipMemcpyHostToDevice,
                         g->stream));
-  pgo_status s = g->opt.precision == PGO_FP64 ? snapshot_or_restore<double>(g, true)
-                                              : snapshot_or_restore<float>(g, true);
-  if (s != PGO_OK) return s;
+  size_t vb[6];
+  state_array_bytes(g, vb);
+  void* dst[6] = {g->p, g->q, g->lam, g->t, g->s, g->z};
+  const void* src[6];
+  int words[6];
+  for (int k = 0; k < 6; ++k) {
+    src[k] = g->snap[k];
+    words[k] = int(vb[k] / 8);
+  }
+  HIPCHK(launch_restore_words(int32_t(g->n), g->gid, g->flag_dev, dst, src, words, g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));  // flags live on the host stack
   return PGO_OK;
 }
@@ -791,6 +884,25 @@ pgo_status check_device_values(pgo_graph* g, const double* dev, size_t count, bo
 
 }  // namespace
 
+namespace {
+
+hipError_t state_io(pgo_graph* g, double* buf, int to_device) {
+  if (g->chordal)
+    return g->opt.precision == PGO_FP64
+               ? launch_state_io_c<double>(viewc<double>(g), buf, to_device, g->stream)
+               : launch_state_io_c<float>(viewc<float>(g), buf, to_device, g->stream);
+  return g->opt.precision == PGO_FP64
+             ? launch_state_io<double>(view<double>(g), buf, to_device, g->stream)
+             : launch_state_io<float>(view<float>(g), buf, to_device, g->stream);
+}
+
+pgo_status quaternion_only(pgo_graph* g, const char* what) {
+  if (!g->chordal) return PGO_OK;
+  return fail(PGO_ESTATE, std::string(what) + " exists for the quaternion model only");
+}
+
+}  // namespace
+
 extern "C" {
 
 void pgo_default_options(pgo_options* o) {
@@ -803,6 +915,7 @@ void pgo_default_options(pgo_options* o) {
   o->schedule = PGO_SCHED_AUTO;
   o->block = 0;
   o->device = 0;
+  o->model = PGO_MODEL_QUAT;
 }
 
 const char* pgo_last_error(void) { return g_err.c_str(); }
@@ -983,9 +1096,13 @@ pgo_status pgo_get_poses(pgo_graph* g, double* R, double* t) {
   if (s != PGO_OK) return s;
   double* dR = R ? g->iobuf : nullptr;
   double* dt = t ? g->iobuf + 9 * g->n : nullptr;
-  hipError_t he = g->opt.precision == PGO_FP64
-                      ? launch_poses<double>(view<double>(g), dR, dt, g->stream)
-                      : launch_poses<float>(view<float>(g), dR, dt, g->stream);
+  hipError_t he;
+  if (g->chordal)
+    he = g->opt.precision == PGO_FP64 ? launch_poses_c<double>(viewc<double>(g), dR, dt, g->stream)
+                                      : launch_poses_c<float>(viewc<float>(g), dR, dt, g->stream);
+  else
+    he = g->opt.precision == PGO_FP64 ? launch_poses<double>(view<double>(g), dR, dt, g->stream)
+                                      : launch_poses<float>(view<float>(g), dR, dt, g->stream);
   if (he != hipSuccess) return hip_fail(he, "poses");
   if (R) HIPCHK(hipMemcpyAsync(R, dR, sizeof(double) * 9 * g->n, hipMemcpyDeviceToHost, g->stream));
   if (t) HIPCHK(hipMemcpyAsync(t, dt, sizeof(double) * 3 * g->n, hipMemcpyDeviceToHost, g->stream));
@@ -998,12 +1115,10 @@ pgo_status pgo_get_state(pgo_graph* g, double* state) {
   HIPCHK(hipSetDevice(g->device));
   pgo_status s = ensure_iobuf(g);
   if (s != PGO_OK) return s;
-  hipError_t he = g->opt.precision == PGO_FP64
-                      ? launch_state_io<double>(view<double>(g), g->iobuf, 0, g->stream)
-                      : launch_state_io<float>(view<float>(g), g->iobuf, 0, g->stream);
+  hipError_t he = state_io(g, g->iobuf, 0);
   if (he != hipSuccess) return hip_fail(he, "state_io");
-  HIPCHK(hipMemcpyAsync(state, g->iobuf, sizeof(double) * 21 * g->n, hipMemcpyDeviceToHost,
-                        g->stream));
+  HIPCHK(hipMemcpyAsync(state, g->iobuf, sizeof(double) * state_width(g) * g->n,
+                        hipMemcpyDeviceToHost, g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
   return PGO_OK;
 }
@@ -1013,11 +1128,9 @@ pgo_status pgo_set_state(pgo_graph* g, const double* state) {
   HIPCHK(hipSetDevice(g->device));
   pgo_status s = ensure_iobuf(g);
   if (s != PGO_OK) return s;
-  HIPCHK(hipMemcpyAsync(g->iobuf, state, sizeof(double) * 21 * g->n, hipMemcpyHostToDevice,
-                        g->stream));
-  hipError_t he = g->opt.precision == PGO_FP64
-                      ? launch_state_io<double>(view<double>(g), g->iobuf, 1, g->stream)
-                      : launch_state_io<float>(view<float>(g), g->iobuf, 1, g->stream);
+  HIPCHK(hipMemcpyAsync(g->iobuf, state, sizeof(double) * state_width(g) * g->n,
+                        hipMemcpyHostToDevice, g->stream));
+  hipError_t he = state_io(g, g->iobuf, 1);
   if (he != hipSuccess) return hip_fail(he, "state_io");
   HIPCHK(hipStreamSynchronize(g->stream));
   g->have_prev = false;
@@ -1027,18 +1140,21 @@ pgo_status pgo_set_state(pgo_graph* g, const double* state) {
 pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat0) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
   HIPCHK(hipSetDevice(g->device));
+  const size_t w = g->chordal ? 9 : 4;
+  const void* e_src = g->chordal ? static_cast<const void*>(g->R9) : g->qe;
+  const void* v_src = g->chordal ? static_cast<const void*>(g->P0) : g->p0;
   if (edge_quat && g->m)
-    HIPCHK(hipMemcpyAsync(edge_quat, g->qe, sizeof(double) * 4 * g->m, hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(edge_quat, e_src, sizeof(double) * w * g->m, hipMemcpyDeviceToHost,
                           g->stream));
   if (vertex_quat0)
-    HIPCHK(hipMemcpyAsync(vertex_quat0, g->p0, sizeof(double) * 4 * g->n, hipMemcpyDeviceToHost,
+    HIPCHK(hipMemcpyAsync(vertex_quat0, v_src, sizeof(double) * w * g->n, hipMemcpyDeviceToHost,
                           g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));
   return PGO_OK;
 }
 
 pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
-                    int32_t* schedule, int32_t* block) {
+                    int32_t* schedule, int32_t* block, int32_t* model) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
   if (n) *n = g->n;
   if (m) *m = g->m;
@@ -1046,6 +1162,7 @@ pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* p
   if (precision) *precision = g->opt.precision;
   if (schedule) *schedule = g->sched;
   if (block) *block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
+  if (model) *model = g->opt.model;
   return PGO_OK;
 }
 
@@ -1055,7 +1172,7 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
   if (!(std::isfinite(beta) && beta > 0.0)) return fail(PGO_EINVAL, "beta must be finite and > 0");
   if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
   HIPCHK(hipSetDevice(g->device));
-  std::vector<double> saved(size_t(21) * g->n);
+  std::vector<double> saved(size_t(state_width(g)) * g->n);
   pgo_status s = pgo_get_state(g, saved.data());
   if (s != PGO_OK) return s;
   struct Cand {
@@ -1099,9 +1216,10 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
 pgo_status pgo_set_edge_params(pgo_graph* g, const double* kappa, const double* tau,
                                const double* tm, const double* omega) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  pgo_status s = quaternion_only(g, "pgo_set_edge_params");
+  if (s != PGO_OK) return s;
   HIPCHK(hipSetDevice(g->device));
   const size_t m = size_t(g->m);
-  pgo_status s;
   if (kappa && (s = check_device_values(g, kappa, m, true, "kappa")) != PGO_OK) return s;
   if (tau && (s = check_device_values(g, tau, m, true, "tau")) != PGO_OK) return s;
   if (tm && (s = check_device_values(g, tm, 3 * m, false, "tm")) != PGO_OK) return s;
@@ -1124,9 +1242,15 @@ pgo_status pgo_set_edge_params(pgo_graph* g, const double* kappa, const double* 
 pgo_status pgo_reset_state(pgo_graph* g) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
   HIPCHK(hipSetDevice(g->device));
-  hipError_t he = g->opt.precision == PGO_FP64
-                      ? launch_init_state<double>(view<double>(g), g->p0, g->t0dev, g->stream)
-                      : launch_init_state<float>(view<float>(g), g->p0, g->t0dev, g->stream);
+  hipError_t he;
+  if (g->chordal)
+    he = g->opt.precision == PGO_FP64
+             ? launch_init_state_c<double>(viewc<double>(g), g->P0, g->t0dev, g->stream)
+             : launch_init_state_c<float>(viewc<float>(g), g->P0, g->t0dev, g->stream);
+  else
+    he = g->opt.precision == PGO_FP64
+             ? launch_init_state<double>(view<double>(g), g->p0, g->t0dev, g->stream)
+             : launch_init_state<float>(view<float>(g), g->p0, g->t0dev, g->stream);
   if (he != hipSuccess) return hip_fail(he, "reset_state");
   HIPCHK(hipStreamSynchronize(g->stream));
   g->have_prev = false;
@@ -1137,15 +1261,15 @@ pgo_status pgo_reset_state(pgo_graph* g) {
 pgo_status pgo_get_state_dev(pgo_graph* g, double* state_dev) {
   if (!g || !state_dev) return fail(PGO_EINVAL, "NULL argument");
   HIPCHK(hipSetDevice(g->device));
-  hipError_t he = g->opt.precision == PGO_FP64
-                      ? launch_state_io<double>(view<double>(g), state_dev, 0, g->stream)
-                      : launch_state_io<float>(view<float>(g), state_dev, 0, g->stream);
+  hipError_t he = state_io(g, state_dev, 0);
   if (he != hipSuccess) return hip_fail(he, "state_io");
   return PGO_OK;
 }
 
 pgo_status pgo_forward_record(pgo_graph* g, int32_t K, double beta, double gamma, int32_t C) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
+  pgo_status qs = quaternion_only(g, "pgo_forward_record");
+  if (qs != PGO_OK) return qs;
   if (K < 1 || C < 1) return fail(PGO_EINVAL, "K and C must be >= 1");
   if (!(std::isfinite(beta) && beta > 0.0)) return fail(PGO_EINVAL, "beta must be finite and > 0");
   if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
@@ -1173,6 +1297,8 @@ pgo_status pgo_forward_record(pgo_graph* g, int32_t K, double beta, double gamma
 pgo_status pgo_adjoint(pgo_graph* g, const double* dL_dstate, double* g_kappa, double* g_tau,
                        double* g_tm, double* g_omega, double* dL_dstate0) {
   if (!g || !dL_dstate) return fail(PGO_EINVAL, "NULL argument");
+  pgo_status qs = quaternion_only(g, "pgo_adjoint");
+  if (qs != PGO_OK) return qs;
   if (g->rec_K < 1) return fail(PGO_ESTATE, "no recorded forward pass (call pgo_forward_record)");
   HIPCHK(hipSetDevice(g->device));
   pgo_status s = ensure_adjoint_buffers(g);

@@ -1,0 +1,544 @@
+// The PRADMM splitting applied to the chordal pose-graph cost: rotations as
+// 3x3 matrices, the chordal distance of App. A.4 on every rotation
+// measurement, translations as in model (1):
+//
+//   F(R, t) = sum_e tau_e |t_j - t_i - R_i t~_e|^2 + kappa_e |R_i R~_e - R_j|_F^2
+//
+// with duplicates P = Q (P_i in SO(3), Q_i a free 3x3 block), t = s and the
+// multipliers Lambda (3x3) and z.  Every block update of the sweep is closed
+// form; the P update is a 3x3 polar factor per vertex:
+//
+//   P  M_i = 2 sum_out (t_j - s_i)(tau t~_e)^T + 2 sum_in Q_l (kappa R~_e)
+//          + beta Q_i + Lambda_i + H1 P_i,
+//      P_i = argmax_{R in SO(3)} <R, M_i> = U diag(1, 1, det(U V^T)) V^T
+//      (|P t~| = |t~| and |P|_F^2 = 3 make f, g and the penalty linear in P);
+//   Q  Q_i = (2 sum_out P_j (kappa R~_e)^T + beta P_i - Lambda_i + H2 Q_i)
+//            / (cQ_i + beta + H2),   Lambda_i -= gamma beta (P_i - Q_i);
+//   T  t_i = (2 sum_in (tau s_l + P_l (tau t~_e)) + beta s_i + z_i + H3 t_i)
+//            / (cT_i + beta + H3);
+//   S  s_i = (2 sum_out (tau t_j - P_i (tau t~_e)) + beta t_i - z_i + H4 s_i)
+//            / (cS_i + beta + H4),   z_i -= gamma beta (t_i - s_i).
+//
+// The schedule is the quaternion model's: P, then per sweep Q, T and S fused
+// with the next sweep's P (P reads neighbours' t and Q only, both final
+// before S starts), one thread per vertex, in-place and race-free, sums in
+// edge order without atomics (bitwise identical across schedules).
+//
+// FP32 path: M_i is summed in float and its polar factor taken in float;
+// when the factor is ill-conditioned relative to the size of the terms
+// (gap = sigma_2 + sign(det M) sigma_3 below 1e-2 of the L1 size of all
+// terms), M_i is summed again in double from the stored float values and
+// factored in double.
+#include <algorithm>
+
+#include "internal.hpp"
+#include "polar.hpp"
+
+namespace pgo {
+
+namespace {
+
+template <typename A, typename T>
+__device__ __forceinline__ void ld9(const R3<T>& m, A out[9]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const P4<T> row = m.r[r];
+    out[3 * r] = A(row.x);
+    out[3 * r + 1] = A(row.y);
+    out[3 * r + 2] = A(row.z);
+  }
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ R3<T> st9(const A m[9]) {
+  R3<T> o;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) o.r[r] = P4<T>{T(m[3 * r]), T(m[3 * r + 1]), T(m[3 * r + 2]), T(0)};
+  return o;
+}
+
+template <typename A>
+__device__ __forceinline__ A l1_9(const A m[9]) {
+  A s = A(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s += fabs(m[k]);
+  return s;
+}
+
+// M_i of the P update in accumulation type A from the state in type T.
+// mag collects the L1 size of every term (FP32 conditioning check only).
+template <typename A, typename T, bool kMag>
+__device__ void p_matrix(const DevChordal<T>& g, int i, const SweepParams& sp, const R3<T>& Qi_,
+                         const P4<T>& si_, const R3<T>& Pi_, const R3<T>& Li_, A M[9], A& mag) {
+  A acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = A(0);
+  const A sx = A(si_.x), sy = A(si_.y), sz = A(si_.z);
+  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
+    const P4<T> tj = g.t[g.o_nbr[e]];
+    const P4<T> u = g.o_tt[e];
+    const A d[3] = {A(tj.x) - sx, A(tj.y) - sy, A(tj.z) - sz};
+    const A uu[3] = {A(u.x), A(u.y), A(u.z)};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[3 * r + c] += d[r] * uu[c];
+    if (kMag)
+      mag += (fabs(d[0]) + fabs(d[1]) + fabs(d[2])) * (fabs(uu[0]) + fabs(uu[1]) + fabs(uu[2]));
+  }
+  for (int e = g.i_ptr[i]; e < g.i_ptr[i + 1]; ++e) {
+    A Ql[9], W[9];
+    ld9<A>(g.Q[g.i_nbr[e]], Ql);
+    ld9<A>(g.i_R[e], W);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        acc[3 * r + c] += Ql[3 * r] * W[c] + Ql[3 * r + 1] * W[3 + c] + Ql[3 * r + 2] * W[6 + c];
+    if (kMag) mag += l1_9(Ql) * l1_9(W);
+  }
+  A Qi[9], Pi[9], Li[9];
+  ld9<A>(Qi_, Qi);
+  ld9<A>(Pi_, Pi);
+  ld9<A>(Li_, Li);
+  const A b = A(sp.beta), h = A(sp.h1);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) M[k] = A(2) * acc[k] + b * Qi[k] + Li[k] + h * Pi[k];
+  if (kMag) mag = A(2) * mag + b * l1_9(Qi) + l1_9(Li) + h * l1_9(Pi);
+}
+
+// sigma_2 + sign(det M) sigma_3 with the singular values sorted descending:
+// the smallest denominator in the derivative of the SO(3) factor.
+template <typename A>
+__device__ __forceinline__ A polar_gap(const A M[9], const A sig[3]) {
+  A a = sig[0], b = sig[1], c = sig[2];
+  if (a < b) { const A t = a; a = b; b = t; }
+  if (b < c) { const A t = b; b = c; c = t; }
+  if (a < b) { const A t = a; a = b; b = t; }
+  return det3<A>(M) >= A(0) ? b + c : b - c;
+}
+
+// P update of vertex i from its own values (passed in, as the fused S+P
+// phase has them in registers).  P_i is kept when M_i = 0.
+template <typename T>
+__device__ void vertex_P_own(const DevChordal<T>& g, int i, const SweepParams& sp,
+                             const R3<T>& Qi, const P4<T>& si, const R3<T>& Pi, const R3<T>& Li) {
+  constexpr bool kF32 = sizeof(T) == 4;
+  T M[9], R[9], sig[3], mag = T(0);
+  p_matrix<T, T, kF32>(g, i, sp, Qi, si, Pi, Li, M, mag);
+  polar3<T>(M, R, sig);
+  if (kF32 && !(polar_gap<T>(M, sig) >= T(1e-2) * mag)) {
+    double Md[9], Rd[9], sd[3], dm = 0.0;
+    p_matrix<double, T, false>(g, i, sp, Qi, si, Pi, Li, Md, dm);
+    polar3<double>(Md, Rd, sd);
+    if (sd[0] > 0.0 || sd[1] > 0.0 || sd[2] > 0.0) g.P[i] = st9<T, double>(Rd);
+    return;
+  }
+  if (sig[0] > T(0) || sig[1] > T(0) || sig[2] > T(0)) g.P[i] = st9<T, T>(R);
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, int i, const SweepParams& sp,
+                                         bool save, R3<T>& lam, T cQ) {
+  T acc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) acc[k] = T(0);
+  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
+    T Pj[9], W[9];
+    ld9<T>(g.P[g.o_nbr[e]], Pj);
+    ld9<T>(g.o_R[e], W);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)  // (P_j W^T)[r][c] = sum_k P_j[r][k] W[c][k]
+        acc[3 * r + c] += Pj[3 * r] * W[3 * c] + Pj[3 * r + 1] * W[3 * c + 1] +
+                          Pj[3 * r + 2] * W[3 * c + 2];
+  }
+  T Pi[9], Qi[9], Li[9], Qn[9], Ln[9];
+  const R3<T> Qold = g.Q[i];
+  ld9<T>(g.P[i], Pi);
+  ld9<T>(Qold, Qi);
+  ld9<T>(lam, Li);
+  const T b = T(sp.beta), h = T(sp.h2);
+  const T a = cQ + b + h;
+  const T gb = T(sp.gamma * sp.beta);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    Qn[k] = (T(2) * acc[k] + b * Pi[k] - Li[k] + h * Qi[k]) / a;
+    Ln[k] = Li[k] - gb * (Pi[k] - Qn[k]);
+  }
+  if (save) {
+    g.Q_prev[i] = Qold;
+    g.L_prev[i] = lam;
+  }
+  g.Q[i] = st9<T, T>(Qn);
+  lam = st9<T, T>(Ln);
+}
+
+template <typename T>
+__device__ __forceinline__ V3<T> mat_vec(const R3<T>& m, const P4<T>& v) {
+  return {m.r[0].x * v.x + m.r[0].y * v.y + m.r[0].z * v.z,
+          m.r[1].x * v.x + m.r[1].y * v.y + m.r[1].z * v.z,
+          m.r[2].x * v.x + m.r[2].y * v.y + m.r[2].z * v.z};
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_T(const DevChordal<T>& g, int i, const SweepParams& sp,
+                                         bool save, const V3<T>& zi, T cT) {
+  V3<T> acc = {T(0), T(0), T(0)};
+  for (int e = g.i_ptr[i]; e < g.i_ptr[i + 1]; ++e) {
+    const int l = g.i_nbr[e];
+    const P4<T> u = g.i_tt[e];
+    const P4<T> sl = g.s[l];
+    const V3<T> c = mat_vec(g.P[l], u);  // P_l (tau t~)
+    acc.x += u.u * sl.x + c.x;
+    acc.y += u.u * sl.y + c.y;
+    acc.z += u.u * sl.z + c.z;
+  }
+  const P4<T> ti = g.t[i], si = g.s[i];
+  const T b = T(sp.beta), h = T(sp.h3);
+  const T a = cT + b + h;
+  if (save) g.t_prev[i] = ti;
+  g.t[i] = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+                 (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
+                 (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
+}
+
+template <typename T>
+__device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const SweepParams& sp,
+                                         bool save, V3<T>& z, T cS, R3<T>* P_out = nullptr,
+                                         R3<T>* Q_out = nullptr, P4<T>* s_out = nullptr) {
+  const R3<T> Pi = g.P[i];
+  V3<T> acc = {T(0), T(0), T(0)};
+  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
+    const P4<T> u = g.o_tt[e];
+    const P4<T> tj = g.t[g.o_nbr[e]];
+    const V3<T> c = mat_vec(Pi, u);  // P_i (tau t~)
+    acc.x += u.u * tj.x - c.x;
+    acc.y += u.u * tj.y - c.y;
+    acc.z += u.u * tj.z - c.z;
+  }
+  const P4<T> ti = g.t[i], si = g.s[i];
+  const V3<T> zi = z;
+  const T b = T(sp.beta), h = T(sp.h4);
+  const T a = cS + b + h;
+  const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
+                    (T(2) * acc.y + b * ti.y - zi.y + h * si.y) / a,
+                    (T(2) * acc.z + b * ti.z - zi.z + h * si.z) / a};
+  const T gb = T(sp.gamma * sp.beta);
+  if (save) {
+    g.s_prev[i] = si;
+    g.z_prev[i] = pad3(zi);
+  }
+  g.s[i] = pad3(sn);
+  z = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  if (P_out) {
+    *P_out = Pi;
+    *Q_out = g.Q[i];
+    *s_out = pad3(sn);
+  }
+}
+
+template <int PH, typename T>
+__device__ __forceinline__ void phase_c(const DevChordal<T>& g, int i, const SweepParams& sp,
+                                        bool save) {
+  if (PH == 0) vertex_P_own(g, i, sp, g.Q[i], g.s[i], g.P[i], g.L[i]);
+  if (PH == 1) {
+    R3<T> l = g.L[i];
+    vertex_Q(g, i, sp, save, l, g.cQ[i]);
+    g.L[i] = l;
+  }
+  if (PH == 2) vertex_T(g, i, sp, save, v3(g.z[i]), g.cT[i]);
+  if (PH == 3) {
+    V3<T> z = v3(g.z[i]);
+    vertex_S(g, i, sp, save, z, g.cS[i]);
+    g.z[i] = pad3(z);
+  }
+  if (PH == 4) {  // S of this sweep + P of the next
+    V3<T> z = v3(g.z[i]);
+    R3<T> Pi, Qi;
+    P4<T> si;
+    vertex_S(g, i, sp, false, z, g.cS[i], &Pi, &Qi, &si);
+    g.z[i] = pad3(z);
+    vertex_P_own(g, i, sp, Qi, si, Pi, g.L[i]);
+  }
+}
+
+constexpr int kXcds = 8;
+
+// XCD-aware block renumbering (see the quaternion sweep): each XCD walks one
+// contiguous range of vertices.
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, nb = gridDim.x;
+  const int xcd = b % kXcds, local = b / kXcds;
+  const int per = nb / kXcds, rem = nb % kXcds;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+template <int PH, typename T>
+__global__ void k_phase_c(DevChordal<T> g, SweepParams sp, int save) {
+  const int i = xcd_block() * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  if (sp.active && !sp.active[g.gid[i]]) return;
+  if (sp.beta_g) sp.beta = sp.beta_g[g.gid[i]];
+  phase_c<PH, T>(g, i, sp, save != 0);
+}
+
+template <typename T>
+__global__ void k_graph_sweeps_c(DevChordal<T> g, const int32_t* __restrict__ voff,
+                                 const int32_t* __restrict__ order, int k, SweepParams sp) {
+  const int gr = order[blockIdx.x];
+  const int v0 = voff[gr], v1 = voff[gr + 1];
+  if (sp.active && !sp.active[gr]) return;
+  if (sp.beta_g) sp.beta = sp.beta_g[gr];
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<0, T>(g, i, sp, false);
+  __syncthreads();
+  for (int it = 0; it < k; ++it) {
+    const bool save = it == k - 1;
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<1, T>(g, i, sp, save);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<2, T>(g, i, sp, save);
+    __syncthreads();
+    if (save) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<3, T>(g, i, sp, true);
+    } else {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<4, T>(g, i, sp, false);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// preparation and state transfer
+// ---------------------------------------------------------------------------
+__global__ void k_project_rot(const double* __restrict__ R, int64_t count, double* __restrict__ out,
+                              uint8_t* __restrict__ bad) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double a[9];
+  for (int k = 0; k < 9; ++k) a[k] = R[9 * i + k];
+  double dev = 0.0;
+  for (int r = 0; r < 3; ++r)
+    for (int s = 0; s < 3; ++s) {
+      const double d = a[r] * a[s] + a[3 + r] * a[3 + s] + a[6 + r] * a[6 + s] - (r == s ? 1.0 : 0.0);
+      dev += d * d;
+    }
+  const bool ok = det3<double>(a) > 0.0 && sqrt(dev) <= 1e-2;
+  bad[i] = ok ? 0 : 1;
+  double rot[9], sig[3];
+  if (ok) {
+    polar3<double>(a, rot, sig);
+  } else {
+    for (int k = 0; k < 9; ++k) rot[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  }
+  for (int k = 0; k < 9; ++k) out[9 * i + k] = rot[k];
+}
+
+template <typename T>
+__global__ void k_fill_edges_c(const int32_t* __restrict__ perm, const int32_t* __restrict__ nbr_src,
+                               const double* __restrict__ R9, const double* __restrict__ tm,
+                               const double* __restrict__ kappa, const double* __restrict__ tau,
+                               int64_t m, int32_t* __restrict__ nbr, P4<T>* __restrict__ tt,
+                               R3<T>* __restrict__ Rw) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int64_t e = perm[k];
+  nbr[k] = nbr_src[e];
+  const double ta = tau[e], ka = kappa[e];
+  tt[k] = P4<T>{T(ta * tm[3 * e]), T(ta * tm[3 * e + 1]), T(ta * tm[3 * e + 2]), T(ta)};
+  double w[9];
+  for (int c = 0; c < 9; ++c) w[c] = ka * R9[9 * e + c];
+  Rw[k] = st9<T, double>(w);
+}
+
+template <typename T>
+__global__ void k_vertex_consts_c(int32_t n, const int32_t* __restrict__ o_ptr,
+                                  const int32_t* __restrict__ o_perm,
+                                  const int32_t* __restrict__ i_ptr,
+                                  const int32_t* __restrict__ i_perm,
+                                  const double* __restrict__ kappa, const double* __restrict__ tau,
+                                  T* __restrict__ cQ, T* __restrict__ cT, T* __restrict__ cS) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double q = 0.0, s = 0.0, t = 0.0;
+  for (int k = o_ptr[i]; k < o_ptr[i + 1]; ++k) {
+    q += kappa[o_perm[k]];
+    s += tau[o_perm[k]];
+  }
+  for (int k = i_ptr[i]; k < i_ptr[i + 1]; ++k) t += tau[i_perm[k]];
+  cQ[i] = T(2.0 * q);
+  cT[i] = T(2.0 * t);
+  cS[i] = T(2.0 * s);
+}
+
+template <typename T>
+__global__ void k_init_state_c(DevChordal<T> g, const double* __restrict__ P0,
+                               const double* __restrict__ t0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  const R3<T> P = st9<T, double>(P0 + 9 * int64_t(i));
+  const P4<T> t = P4<T>{T(t0[3 * i]), T(t0[3 * i + 1]), T(t0[3 * i + 2]), T(0)};
+  const R3<T> Z = {{P4<T>{T(0), T(0), T(0), T(0)}, P4<T>{T(0), T(0), T(0), T(0)},
+                    P4<T>{T(0), T(0), T(0), T(0)}}};
+  const P4<T> z3 = P4<T>{T(0), T(0), T(0), T(0)};
+  g.P[i] = P;
+  g.Q[i] = P;
+  g.L[i] = Z;
+  g.t[i] = t;
+  g.s[i] = t;
+  g.z[i] = z3;
+  g.Q_prev[i] = P;
+  g.L_prev[i] = Z;
+  g.t_prev[i] = t;
+  g.s_prev[i] = t;
+  g.z_prev[i] = z3;
+}
+
+template <typename T>
+__global__ void k_state_io_c(DevChordal<T> g, double* __restrict__ buf, int to_device) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  double* b = buf + 36 * int64_t(i);
+  if (to_device) {
+    g.P[i] = st9<T, double>(b);
+    g.Q[i] = st9<T, double>(b + 9);
+    g.t[i] = P4<T>{T(b[18]), T(b[19]), T(b[20]), T(0)};
+    g.s[i] = P4<T>{T(b[21]), T(b[22]), T(b[23]), T(0)};
+    g.L[i] = st9<T, double>(b + 24);
+    g.z[i] = P4<T>{T(b[33]), T(b[34]), T(b[35]), T(0)};
+  } else {
+    double v[9];
+    ld9<double>(g.P[i], v);
+    for (int k = 0; k < 9; ++k) b[k] = v[k];
+    ld9<double>(g.Q[i], v);
+    for (int k = 0; k < 9; ++k) b[9 + k] = v[k];
+    const P4<T> t = g.t[i], s = g.s[i], z = g.z[i];
+    b[18] = double(t.x); b[19] = double(t.y); b[20] = double(t.z);
+    b[21] = double(s.x); b[22] = double(s.y); b[23] = double(s.z);
+    ld9<double>(g.L[i], v);
+    for (int k = 0; k < 9; ++k) b[24 + k] = v[k];
+    b[33] = double(z.x); b[34] = double(z.y); b[35] = double(z.z);
+  }
+}
+
+template <typename T>
+__global__ void k_poses_c(DevChordal<T> g, double* __restrict__ R, double* __restrict__ t) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n) return;
+  if (R) {
+    double v[9];
+    ld9<double>(g.P[i], v);
+    for (int k = 0; k < 9; ++k) R[9 * int64_t(i) + k] = v[k];
+  }
+  if (t) {
+    const P4<T> x = g.t[i];
+    t[3 * int64_t(i)] = double(x.x);
+    t[3 * int64_t(i) + 1] = double(x.y);
+    t[3 * int64_t(i) + 2] = double(x.z);
+  }
+}
+
+dim3 grid_of(int64_t count, int block) { return dim3(unsigned((count + block - 1) / block)); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_phase_sweeps_c(const DevChordal<T>& g, int k, const SweepParams& sp, int block,
+                                 hipStream_t st) {
+  if (g.n <= 0 || k <= 0) return hipSuccess;
+  if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  const int nb = (g.n + block - 1) / block;
+  hipLaunchKernelGGL((k_phase_c<0, T>), dim3(nb), dim3(block), 0, st, g, sp, 0);
+  for (int it = 0; it < k; ++it) {
+    const int save = it == k - 1;
+    hipLaunchKernelGGL((k_phase_c<1, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    hipLaunchKernelGGL((k_phase_c<2, T>), dim3(nb), dim3(block), 0, st, g, sp, save);
+    if (save)
+      hipLaunchKernelGGL((k_phase_c<3, T>), dim3(nb), dim3(block), 0, st, g, sp, 1);
+    else
+      hipLaunchKernelGGL((k_phase_c<4, T>), dim3(nb), dim3(block), 0, st, g, sp, 0);
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return err;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_graph_sweeps_c(const DevChordal<T>& g, const int32_t* voff, const int32_t* order,
+                                 int G, int k, const SweepParams& sp, int block, hipStream_t st) {
+  if (G <= 0 || k <= 0) return hipSuccess;
+  if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_graph_sweeps_c<T>), dim3(G), dim3(block), 0, st, g, voff, order, k, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_rot(const double* R, int64_t count, double* out, uint8_t* bad,
+                              hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_project_rot, grid_of(count, 256), dim3(256), 0, st, R, count, out, bad);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_edges_c(const int32_t* perm, const int32_t* nbr_src, const double* R9,
+                               const double* tm, const double* kappa, const double* tau, int64_t m,
+                               int32_t* nbr, P4<T>* tt, R3<T>* Rw, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_fill_edges_c<T>), grid_of(m, 256), dim3(256), 0, st, perm, nbr_src, R9, tm,
+                     kappa, tau, m, nbr, tt, Rw);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_vertex_consts_c(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
+                                  const int32_t* i_ptr, const int32_t* i_perm, const double* kappa,
+                                  const double* tau, T* cQ, T* cT, T* cS, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_vertex_consts_c<T>), grid_of(n, 256), dim3(256), 0, st, n, o_ptr, o_perm,
+                     i_ptr, i_perm, kappa, tau, cQ, cT, cS);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_init_state_c(const DevChordal<T>& g, const double* P0, const double* t0,
+                               hipStream_t st) {
+  if (g.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_init_state_c<T>), grid_of(g.n, 256), dim3(256), 0, st, g, P0, t0);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_state_io_c(const DevChordal<T>& g, double* buf, int to_device, hipStream_t st) {
+  if (g.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_state_io_c<T>), grid_of(g.n, 256), dim3(256), 0, st, g, buf, to_device);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_poses_c(const DevChordal<T>& g, double* R, double* t, hipStream_t st) {
+  if (g.n <= 0) return hipSuccess;
+  hipLaunchKernelGGL((k_poses_c<T>), grid_of(g.n, 256), dim3(256), 0, st, g, R, t);
+  return hipGetLastError();
+}
+
+#define PGO_CHORDAL_INST(T)                                                                      \
+  template hipError_t launch_phase_sweeps_c<T>(const DevChordal<T>&, int, const SweepParams&,   \
+                                               int, hipStream_t);                                \
+  template hipError_t launch_graph_sweeps_c<T>(const DevChordal<T>&, const int32_t*,            \
+                                               const int32_t*, int, int, const SweepParams&,     \
+                                               int, hipStream_t);                                \
+  template hipError_t launch_fill_edges_c<T>(const int32_t*, const int32_t*, const double*,     \
+                                             const double*, const double*, const double*,       \
+                                             int64_t, int32_t*, P4<T>*, R3<T>*, hipStream_t);    \
+  template hipError_t launch_vertex_consts_c<T>(int32_t, const int32_t*, const int32_t*,        \
+                                                const int32_t*, const int32_t*, const double*,  \
+                                                const double*, T*, T*, T*, hipStream_t);         \
+  template hipError_t launch_init_state_c<T>(const DevChordal<T>&, const double*, const double*, \
+                                             hipStream_t);                                       \
+  template hipError_t launch_state_io_c<T>(const DevChordal<T>&, double*, int, hipStream_t);    \
+  template hipError_t launch_poses_c<T>(const DevChordal<T>&, double*, double*, hipStream_t);
+
+PGO_CHORDAL_INST(float)
+PGO_CHORDAL_INST(double)
+
+}  // namespace pgo

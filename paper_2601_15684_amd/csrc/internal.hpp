@@ -56,6 +56,39 @@ struct SweepParams {
   const int32_t* active;  // per-graph run flags (device, G values) or nullptr = all run
 };
 
+// Device view for the rotation-matrix (chordal) model: the same edge order
+// and SoA layout, with 3x3 blocks in place of quaternions.  Edge record
+//   nbr, tt = (tau t~_e, tau_e), R = kappa_e R~_e
+// and vertex constants cQ_i = 2 sum_out kappa, cT_i = 2 sum_in tau,
+// cS_i = 2 sum_out tau.
+template <typename T>
+struct DevChordal {
+  int32_t n;
+  const int32_t* gid;
+  const int32_t* o_ptr;
+  const int32_t* o_nbr;
+  const P4<T>* o_tt;
+  const R3<T>* o_R;
+  const int32_t* i_ptr;
+  const int32_t* i_nbr;
+  const P4<T>* i_tt;
+  const R3<T>* i_R;
+  const T* cQ;
+  const T* cT;
+  const T* cS;
+  R3<T>* P;
+  R3<T>* Q;
+  R3<T>* L;
+  P4<T>* t;
+  P4<T>* s;
+  P4<T>* z;
+  R3<T>* Q_prev;
+  R3<T>* L_prev;
+  P4<T>* t_prev;
+  P4<T>* s_prev;
+  P4<T>* z_prev;
+};
+
 // Launchers (sweep.hip).  Every launcher checks its own configuration and
 // returns the HIP status of the launch.
 template <typename T>
@@ -70,11 +103,6 @@ hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const 
 
 // Per-graph snapshot restore: every vertex of a graph with flag[g] != 0 gets
 // its state (p, q, lambda, t, s, z) back from the snapshot arrays.
-template <typename T>
-hipError_t launch_restore(const DevGraph<T>& g, const Q4<T>* p, const Q4<T>* q, const Q4<T>* lam,
-                          const P4<T>* t, const P4<T>* s, const P4<T>* z, const int32_t* flag,
-                          hipStream_t st);
-
 // Boundary preparation (prep.hip), FP64.
 // bad[i] = 1 where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
 // device-to-device copy as a kernel (8-byte aligned, size a multiple of 8)
@@ -106,6 +134,40 @@ hipError_t launch_state_io(const DevGraph<T>& g, double* buf, int to_device, hip
 template <typename T>
 hipError_t launch_poses(const DevGraph<T>& g, double* R, double* t, hipStream_t st);
 
+// Chordal model (chordal.hip): sweeps, preparation and state transfer.
+template <typename T>
+hipError_t launch_phase_sweeps_c(const DevChordal<T>& g, int k, const SweepParams& sp, int block,
+                                 hipStream_t st);
+template <typename T>
+hipError_t launch_graph_sweeps_c(const DevChordal<T>& g, const int32_t* voff, const int32_t* order,
+                                 int G, int k, const SweepParams& sp, int block, hipStream_t st);
+// projection of 3x3 matrices onto SO(3) with the validity rule of
+// launch_rot_to_quat (det > 0 and ||A^T A - I||_F <= 1e-2, else bad[i] = 1)
+hipError_t launch_project_rot(const double* R, int64_t count, double* out, uint8_t* bad,
+                              hipStream_t st);
+template <typename T>
+hipError_t launch_fill_edges_c(const int32_t* perm, const int32_t* nbr_src, const double* R9,
+                               const double* tm, const double* kappa, const double* tau, int64_t m,
+                               int32_t* nbr, P4<T>* tt, R3<T>* Rw, hipStream_t st);
+template <typename T>
+hipError_t launch_vertex_consts_c(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
+                                  const int32_t* i_ptr, const int32_t* i_perm, const double* kappa,
+                                  const double* tau, T* cQ, T* cT, T* cS, hipStream_t st);
+template <typename T>
+hipError_t launch_init_state_c(const DevChordal<T>& g, const double* P0, const double* t0,
+                               hipStream_t st);
+// n x 36 doubles per vertex: P (9) Q (9) t (3) s (3) Lambda (9) z (3)
+template <typename T>
+hipError_t launch_state_io_c(const DevChordal<T>& g, double* buf, int to_device, hipStream_t st);
+template <typename T>
+hipError_t launch_poses_c(const DevChordal<T>& g, double* R, double* t, hipStream_t st);
+
+// Restores the six state arrays of every vertex whose graph is flagged;
+// words[k] = 8-byte words per vertex of array k.
+hipError_t launch_restore_words(int32_t n, const int32_t* gid, const int32_t* flag,
+                                void* const* dst, const void* const* src, const int* words,
+                                hipStream_t st);
+
 // FP64 reductions (reduce.hip).  Items are split into chunks that never cross
 // a graph boundary; chunk c covers [cbeg[c], cend[c]) of graph cgraph[c].
 // Partial sums of a chunk are reduced in a fixed order, then each graph sums
@@ -117,6 +179,7 @@ struct EdgeF64 {  // caller-order FP64 copy of the prepared edges for the cost
   const double* tm;
   const double* kappa;
   const double* tau;
+  const double* R9;  // chordal model: projected measured rotations (m x 9), else unused
 };
 // Per-graph reduction output, kRedVals doubles per graph:
 enum RedIdx {
@@ -142,6 +205,13 @@ hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
                          const int64_t* vc_end, int n_vchunks, double* partial_e,
                          double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
                          int G, double* out, hipStream_t st);
+
+template <typename T>
+hipError_t launch_reduce_c(const DevChordal<T>& g, const EdgeF64& e, int have_prev,
+                           const int64_t* ec_beg, const int64_t* ec_end, int n_echunks,
+                           const int64_t* vc_beg, const int64_t* vc_end, int n_vchunks,
+                           double* partial_e, double* partial_v, const int32_t* g_ec_off,
+                           const int32_t* g_vc_off, int G, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Reverse mode (adjoint.hip)

@@ -336,4 +336,35 @@ hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st)
   return hipGetLastError();
 }
 
+struct RestoreArgs {
+  uint64_t* dst[6];
+  const uint64_t* src[6];
+  int words[6];
+};
+
+__global__ void k_restore_words(int32_t n, const int32_t* __restrict__ gid,
+                                const int32_t* __restrict__ flag, RestoreArgs a) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !flag[gid[i]]) return;
+  for (int k = 0; k < 6; ++k) {
+    const int w = a.words[k];
+    for (int c = 0; c < w; ++c) a.dst[k][int64_t(i) * w + c] = a.src[k][int64_t(i) * w + c];
+  }
+}
+
+hipError_t launch_restore_words(int32_t n, const int32_t* gid, const int32_t* flag,
+                                void* const* dst, const void* const* src, const int* words,
+                                hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  RestoreArgs a;
+  for (int k = 0; k < 6; ++k) {
+    if (words[k] < 0 || words[k] > 16) return hipErrorInvalidValue;
+    a.dst[k] = static_cast<uint64_t*>(dst[k]);
+    a.src[k] = static_cast<const uint64_t*>(src[k]);
+    a.words[k] = words[k];
+  }
+  hipLaunchKernelGGL(k_restore_words, dim3((n + 255) / 256), dim3(256), 0, st, n, gid, flag, a);
+  return hipGetLastError();
+}
+
 }  // namespace pgo

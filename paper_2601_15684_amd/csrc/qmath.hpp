@@ -25,6 +25,13 @@ struct V3 {
   T x, y, z;
 };
 
+// 3x3 matrix as three padded rows (row r = (m[r][0], m[r][1], m[r][2], 0)),
+// so a row is one aligned 16/32-byte access.
+template <typename T>
+struct R3 {
+  P4<T> r[3];
+};
+
 template <typename T>
 __device__ __forceinline__ Q4<T> qmul(const Q4<T>& a, const Q4<T>& b) {
   return {a.w * b.w - a.x * b.x - a.y * b.y - a.z * b.z,

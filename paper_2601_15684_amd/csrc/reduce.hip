@@ -1,5 +1,6 @@
-// FP64 reductions per graph: the cost of model (1) at (p, t) and the
-// residual sums behind App. E.1's iteration residual.  Work is cut into
+// FP64 reductions per graph: the cost of model (1) at (p, t) (or the
+// chordal cost at (P, t)) and the residual sums behind App. E.1's iteration
+// residual.  Work is cut into
 // chunks that never straddle two graphs; each workgroup reduces one chunk
 // with a fixed-shape tree, then one thread per graph adds its chunks in
 // order.  No atomics, so every run gives the same bits.
@@ -144,7 +145,128 @@ __global__ void k_red_finish(const double* __restrict__ pe, const double* __rest
   for (int q = 0; q < kVertVals; ++q) out[kRedVals * int64_t(gr) + kEdgeVals + q] = v[q];
 }
 
+// --- chordal model -----------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void rowsd(const R3<T>& m, double o[9]) {
+  for (int r = 0; r < 3; ++r) {
+    o[3 * r] = double(m.r[r].x);
+    o[3 * r + 1] = double(m.r[r].y);
+    o[3 * r + 2] = double(m.r[r].z);
+  }
+}
+
+// tau |a_j - b_i - A_i t~|^2 + kappa |B_i R~ - P_j|_F^2: the cost with
+// (A, B, b) = (P, P, t), the split f + g with (A, B, b) = (P, Q, s).
+template <typename T>
+__device__ double edge_chordal(const EdgeF64& E, int64_t e, const R3<T>& Ai_, const R3<T>& Bi_,
+                               const R3<T>& Pj_, const P4<T>& bi, const P4<T>& tj) {
+  double A[9], B[9], Pj[9];
+  rowsd(Ai_, A);
+  rowsd(Bi_, B);
+  rowsd(Pj_, Pj);
+  const double* Rm = E.R9 + 9 * e;
+  const double u[3] = {E.tm[3 * e], E.tm[3 * e + 1], E.tm[3 * e + 2]};
+  const double d[3] = {double(tj.x) - double(bi.x), double(tj.y) - double(bi.y),
+                       double(tj.z) - double(bi.z)};
+  double rt = 0.0, rr = 0.0;
+  for (int r = 0; r < 3; ++r) {
+    const double x = d[r] - (A[3 * r] * u[0] + A[3 * r + 1] * u[1] + A[3 * r + 2] * u[2]);
+    rt += x * x;
+    for (int c = 0; c < 3; ++c) {
+      const double y = B[3 * r] * Rm[c] + B[3 * r + 1] * Rm[3 + c] + B[3 * r + 2] * Rm[6 + c] -
+                       Pj[3 * r + c];
+      rr += y * y;
+    }
+  }
+  return E.tau[e] * rt + E.kappa[e] * rr;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRB) k_red_edges_c(DevChordal<T> g, EdgeF64 E,
+                                                      const int64_t* __restrict__ beg,
+                                                      const int64_t* __restrict__ end,
+                                                      double* __restrict__ partial) {
+  __shared__ double sh[kEdgeVals][kRB];
+  double v[kEdgeVals] = {0.0, 0.0};
+  const int c = blockIdx.x;
+  for (int64_t e = beg[c] + threadIdx.x; e < end[c]; e += kRB) {
+    const int i = E.ei[e], j = E.ej[e];
+    const R3<T> Pi = g.P[i], Pj = g.P[j];
+    v[0] += edge_chordal(E, e, Pi, Pi, Pj, g.t[i], g.t[j]);
+    v[1] += edge_chordal(E, e, Pi, g.Q[i], Pj, g.s[i], g.t[j]);
+  }
+  block_sum<kEdgeVals>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kEdgeVals; ++k) partial[kEdgeVals * int64_t(c) + k] = v[k];
+}
+
+template <typename T>
+__device__ __forceinline__ double d2m(const R3<T>& a, const R3<T>& b) {
+  double s = 0.0;
+  for (int r = 0; r < 3; ++r) s += d2<T, P4<T>>(a.r[r], b.r[r]);
+  return s;
+}
+
+template <typename T>
+__device__ __forceinline__ double dotm(const R3<T>& l, const R3<T>& a, const R3<T>& b) {
+  double s = 0.0;
+  for (int r = 0; r < 3; ++r) s += dot3(l.r[r], a.r[r], b.r[r]);
+  return s;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRB) k_red_vertices_c(DevChordal<T> g, int have_prev,
+                                                         const int64_t* __restrict__ beg,
+                                                         const int64_t* __restrict__ end,
+                                                         double* __restrict__ partial) {
+  __shared__ double sh[kVertVals][kRB];
+  double v[kVertVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  const int c = blockIdx.x;
+  for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
+    v[0] += d2m(g.P[i], g.Q[i]);
+    v[1] += d2<T, P4<T>>(g.t[i], g.s[i]);
+    v[7] += dotm(g.L[i], g.P[i], g.Q[i]);
+    v[8] += dot3(g.z[i], g.t[i], g.s[i]);
+    if (have_prev) {
+      v[2] += d2m(g.L[i], g.L_prev[i]);
+      v[3] += d2<T, P4<T>>(g.z[i], g.z_prev[i]);
+      v[4] += d2m(g.Q[i], g.Q_prev[i]);
+      v[5] += d2<T, P4<T>>(g.t[i], g.t_prev[i]);
+      v[6] += d2<T, P4<T>>(g.s[i], g.s_prev[i]);
+    }
+  }
+  block_sum<kVertVals>(v, sh);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kVertVals; ++k) partial[kVertVals * int64_t(c) + k] = v[k];
+}
+
 }  // namespace
+
+template <typename T>
+hipError_t launch_reduce_c(const DevChordal<T>& g, const EdgeF64& e, int have_prev,
+                           const int64_t* ec_beg, const int64_t* ec_end, int n_echunks,
+                           const int64_t* vc_beg, const int64_t* vc_end, int n_vchunks,
+                           double* partial_e, double* partial_v, const int32_t* g_ec_off,
+                           const int32_t* g_vc_off, int G, double* out, hipStream_t st) {
+  if (n_echunks > 0)
+    hipLaunchKernelGGL((k_red_edges_c<T>), dim3(n_echunks), dim3(kRB), 0, st, g, e, ec_beg, ec_end,
+                       partial_e);
+  if (n_vchunks > 0)
+    hipLaunchKernelGGL((k_red_vertices_c<T>), dim3(n_vchunks), dim3(kRB), 0, st, g, have_prev,
+                       vc_beg, vc_end, partial_v);
+  hipLaunchKernelGGL(k_red_finish, dim3((G + 255) / 256), dim3(256), 0, st, partial_e, partial_v,
+                     g_ec_off, g_vc_off, G, out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_reduce_c<float>(const DevChordal<float>&, const EdgeF64&, int,
+                                           const int64_t*, const int64_t*, int, const int64_t*,
+                                           const int64_t*, int, double*, double*, const int32_t*,
+                                           const int32_t*, int, double*, hipStream_t);
+template hipError_t launch_reduce_c<double>(const DevChordal<double>&, const EdgeF64&, int,
+                                            const int64_t*, const int64_t*, int, const int64_t*,
+                                            const int64_t*, int, double*, double*, const int32_t*,
+                                            const int32_t*, int, double*, hipStream_t);
 
 template <typename T>
 hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,

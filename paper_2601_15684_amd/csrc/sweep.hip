@@ -405,39 +405,6 @@ hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const 
   return hipGetLastError();
 }
 
-template <typename T>
-__global__ void k_restore(DevGraph<T> g, const Q4<T>* __restrict__ p, const Q4<T>* __restrict__ q,
-                          const Q4<T>* __restrict__ lam, const P4<T>* __restrict__ t,
-                          const P4<T>* __restrict__ s, const P4<T>* __restrict__ z,
-                          const int32_t* __restrict__ flag) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= g.n || !flag[g.gid[i]]) return;
-  g.p[i] = p[i];
-  g.q[i] = q[i];
-  g.lam[i] = lam[i];
-  g.t[i] = t[i];
-  g.s[i] = s[i];
-  g.z[i] = z[i];
-}
-
-template <typename T>
-hipError_t launch_restore(const DevGraph<T>& g, const Q4<T>* p, const Q4<T>* q, const Q4<T>* lam,
-                          const P4<T>* t, const P4<T>* s, const P4<T>* z, const int32_t* flag,
-                          hipStream_t st) {
-  if (g.n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_restore<T>), dim3((g.n + 255) / 256), dim3(256), 0, st, g, p, q, lam, t, s,
-                     z, flag);
-  return hipGetLastError();
-}
-
-template hipError_t launch_restore<float>(const DevGraph<float>&, const Q4<float>*,
-                                          const Q4<float>*, const Q4<float>*, const P4<float>*,
-                                          const P4<float>*, const P4<float>*, const int32_t*,
-                                          hipStream_t);
-template hipError_t launch_restore<double>(const DevGraph<double>&, const Q4<double>*,
-                                           const Q4<double>*, const Q4<double>*,
-                                           const P4<double>*, const P4<double>*,
-                                           const P4<double>*, const int32_t*, hipStream_t);
 template hipError_t launch_phase_sweeps<float>(const DevGraph<float>&, int, const SweepParams&,
                                                int, hipStream_t);
 template hipError_t launch_phase_sweeps<double>(const DevGraph<double>&, int,

@@ -33,6 +33,7 @@ def test_default_options(pgo):
     o = pgo.pgo_default_options()
     assert (o.h1, o.h2, o.h3, o.h4) == (1.0, 1e-3, 1e-3, 1e-3)
     assert o.precision == pgo.FP64 and o.schedule == pgo.SCHED_AUTO and o.device == 0
+    assert o.model == pgo.MODEL_QUAT
 
 
 def _tiny():
@@ -73,6 +74,7 @@ def test_create_rejects_invalid_input(pgo, mutate, match):
     (dict(precision=7), "precision"),
     (dict(block=100), "block"),
     (dict(schedule=9), "schedule"),
+    (dict(model=5), "model"),
 ])
 def test_create_rejects_invalid_options(pgo, kw, match):
     a = _tiny()

@@ -46,3 +46,28 @@ def test_float32_oracle_error_scales_with_coordinates(monkeypatch, name):
     assert worst >= 1e-7 * L            # and not trivially: the bound is ~the arithmetic's error
     # the error is proportional to the coordinate scale, not an absolute floor
     assert err["t"] >= 1e-8 * float(ref["t"].abs().max())
+
+
+@pytest.mark.parametrize("name", ["grid-1k", "sphere-2.5k", "grid-100k"])
+def test_float32_chordal_oracle_error_scales_with_coordinates(name):
+    """The same bound for the rotation-matrix rendering: its oracle run with
+    every tensor in float32 (the polar factor's SVD included) stays within
+    1e-4 L of its float64 run after 10 sweeps in P, Q, t, s, and not
+    trivially so.  The multipliers sum every sweep's rounded P - Q and
+    t - s; on the 100k-pose grid Lambda/beta departs by ~1.6e-4 L, so the
+    multiplier bound is 1e-3 L."""
+    from oracle import chordal as C
+    g = S.make_config(name)
+    beta = 0.01 * abar(g)
+    Pb, P0, t0 = C.prepare_graph(g)
+    st0 = C.init_state(P0, t0)
+    ref = C.iterate(Pb, st0, 10, beta, 1.4)
+    P32 = {k: (v.float() if torch.is_tensor(v) and v.is_floating_point() else v) for k, v in Pb.items()}
+    lo = C.iterate(P32, {k: v.float() for k, v in st0.items()}, 10, beta, 1.4)
+    L = max(1.0, float(ref["t"].abs().max()) / 10.0)
+    err = {k: float((lo[k].double() - ref[k]).abs().max()) / (beta if k in ("L", "z") else 1.0)
+           for k in ref}
+    worst = max(err.values())
+    assert max(err[k] for k in ("P", "Q", "t", "s")) <= 1e-4 * L, err
+    assert max(err["L"], err["z"]) <= 1e-3 * L, err
+    assert worst >= 1e-7 * L

@@ -74,6 +74,21 @@ def test_adjoint_fp32_matches_fp64_grid_1k(pgo, sched, C):
     assert max(errs.values()) <= 1e-4, errs
 
 
+def test_autograd_on_a_side_stream_matches_default_stream(pgo):
+    """The autograd wrapper orders its library calls with torch's current
+    stream: run under a non-default stream it gives the same bits."""
+    g = S.grid(4, 3, 3, all_pairs=True, sigma_R=0.05, sigma_t=0.1, seed=0)
+    beta = 0.05 * abar(g)
+    L0, g0 = gpu_grads(pgo, g, 10, beta, 3, "fp32", schedule="phase")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        L1, g1 = gpu_grads(pgo, g, 10, beta, 3, "fp32", schedule="phase")
+    torch.cuda.synchronize()
+    assert L0 == L1
+    for k in g0:
+        assert np.array_equal(g0[k], g1[k]), k
+
+
 def test_adjoint_state_gradient_matches_oracle(pgo):
     g = S.random_small(6, 5, seed=4, sigma_R=0.05, sigma_t=0.1)
     beta, K = 0.05 * abar(g), 7
