@@ -7,16 +7,21 @@ circle / grid / sphere topologies, sigma_R ~ U[0.01, 0.1] rad, sigma_t ~
 U[0.01, 0.2] m), FP32 state, one persistent launch of 50 sweeps per step,
 one penalty per graph.  One step is one pass of the whole hot path over the
 batch: 50 sweeps of the four phases (p, q, t, s with the multiplier updates)
-and the FP64 cost/residual reductions of every graph.
+for every graph still running, the FP64 cost/residual/merit reductions of
+every graph and the per-graph penalty check (a graph whose merit rose redoes
+its chunk with a doubled penalty, next to the other graphs' next chunk).
+The warm-up steps and the timed steps each run as one solve call.
 
 Printed: one JSON line with edge-iterations/s (sum over graphs of edges x
-sweeps / wall time of the timed steps), the HBM roofline of the sweep kernel
-(hipEvent-timed launches on the stream the kernel runs on), the plain FP64
-path on the same batch, time to a 1e-6 relative cost gap on the 1000-pose
-grid for both precisions, and the CPU oracle timed on a bounded sample
-(which also checks sampled graphs of the batch against the GPU result).
+accepted sweeps / wall time of the timed steps), the HBM roofline of the
+sweep kernel (hipEvent-timed launches of every graph on the stream the
+kernel runs on), the plain FP64 path and the rotation-matrix rendering on
+the same batch, time to a 1e-6 relative cost gap on the 1000-pose grid for
+both precisions, and the CPU oracle timed on a bounded sample (which also
+checks sampled graphs of the batch against the GPU result).
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 4]
+    python bench.py --steps 0 ...   # only the hipEvent-timed launches (profiling)
 """
 import argparse
 import hashlib
@@ -38,6 +43,9 @@ B_VERTEX = 168  # algorithmic bytes per pose per sweep (21-word FP32 state read 
 # bytes one sweep of this layout streams when every phase reads each array it
 # touches once (per edge / per pose), FP32
 B_EDGE_PHASE, B_VERTEX_PHASE = 116, 448
+# the rotation-matrix rendering: edge (kappa, tau 8, t~ 12, R~ 36, two indices
+# 8) = 64 B; pose state P, Q, Lambda, t, s, z = 36 words read and written
+B_EDGE_CHORDAL, B_VERTEX_CHORDAL = 64, 288
 GAMMA = 1.4
 BETA_SCALE = 0.01
 
@@ -54,10 +62,15 @@ def abar(g):
     return float(d.mean())
 
 
+KERNEL_SOURCES = ("sweep.hip", "chordal.hip", "qmath.hpp", "polar.hpp", "internal.hpp")
+
+
 def source_sha():
+    """Hash of the device sources of the sweep kernels (the byte counters of
+    profiles/traffic.json hold only for the kernels they were taken on)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2601_15684_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES:
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -89,37 +102,39 @@ def copy_calibration(torch, gib=1):
 
 
 def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tune, sched, block,
-              edges_per_graph):
-    """One handle over the whole batch.  A step is one pgo_solve chunk: one
-    persistent launch of `sweeps` sweeps for all graphs, the FP64
-    cost/residual/merit reductions of every graph, and the per-graph merit
-    check (a chunk whose merit rose is undone for that graph, its beta
-    doubled and the chunk rerun).  Warm-up steps settle the penalties;
-    edge-iterations count accepted sweeps only.  The persistent launch alone
-    is also timed with hipEvents on the handle's stream for the roofline."""
+              edges_per_graph, model="quat"):
+    """One handle over the whole batch.  A step is one chunk of the
+    merit-checked solve: one persistent launch of `sweeps` sweeps for every
+    graph still running, the FP64 cost/residual/merit reductions of every
+    graph, and the per-graph merit check (a chunk whose merit rose is undone
+    for that graph and rerun with its beta doubled, alongside the other
+    graphs' next chunk).  The warm-up chunks and the timed chunks each run as
+    one solve call; edge-iterations count accepted sweeps only.  The
+    persistent launch alone is also timed with hipEvents on the handle's
+    stream for the roofline (3 launches of `sweeps` sweeps, every graph)."""
     stream = torch.cuda.Stream()
-    opt = P.pgo_default_options(precision=prec, schedule=sched, block=block)
+    opt = P.pgo_default_options(precision=prec, schedule=sched, block=block, model=model)
     t0 = time.perf_counter()
     h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
                              cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], cat["tau"], opt)
     create_s = time.perf_counter() - t0
     P.pgo_set_stream(h, stream.cuda_stream)
     info = P.pgo_autotune(h, float(np.median(betas)), GAMMA, sweeps=10) if tune else P.pgo_info(h)
-    log(f"[{prec}] created in {create_s:.2f}s, schedule={info['schedule']} block={info['block']}")
+    log(f"[{model}/{prec}] created in {create_s:.2f}s, schedule={info['schedule']} block={info['block']}")
     F0 = P.pgo_cost(h)
     beta = betas.copy()
     accepted = np.zeros(len(betas), np.int64)
-    for _ in range(warmup):
-        beta, done, _ = P.pgo_solve(h, sweeps, sweeps, GAMMA, 0.0, 2.0, beta)
+    if warmup:
+        beta, done, _ = P.pgo_solve(h, warmup * sweeps, sweeps, GAMMA, 0.0, 2.0, beta)
         accepted += done
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     edge_iters = 0
-    with torch.cuda.stream(stream):
-        for k in range(steps):
-            beta, done, _ = P.pgo_solve(h, sweeps, sweeps, GAMMA, 0.0, 2.0, beta)
-            accepted += done
-            edge_iters += int(np.dot(done.astype(np.int64), edges_per_graph))
+    if steps:
+        with torch.cuda.stream(stream):
+            beta, done, _ = P.pgo_solve(h, steps * sweeps, sweeps, GAMMA, 0.0, 2.0, beta)
+        accepted += done
+        edge_iters = int(np.dot(done.astype(np.int64), edges_per_graph))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     res = P.pgo_residuals(h)
@@ -137,6 +152,16 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
     P.pgo_destroy(h)
     return dict(wall=wall, kern_ms=kern_ms, info=info, create_s=create_s, F0=F0, res=res,
                 state=state, accepted=accepted, edge_iters=edge_iters, beta=beta)
+
+
+def health(r, betas):
+    F0, F1 = r["F0"], r["res"][:, 5]
+    return {"graphs_cost_up": int(np.sum(~(F1 <= F0))),
+            "median_final_over_initial": float(np.median(F1 / F0)),
+            "worst_final_over_initial": float(np.max(F1 / F0)),
+            "graphs_beta_raised": int(np.sum(r["beta"] > betas)),
+            "max_beta_over_initial": float(np.max(r["beta"] / betas)),
+            "accepted_sweeps_per_graph": [int(r["accepted"].min()), int(r["accepted"].max())]}
 
 
 def time_to_tol(P, g, prec, beta, F_star, tol=1e-6, check_every=10, cap=20000):
@@ -220,7 +245,8 @@ def cpu_leg(batch, betas, voff, gpu32, gpu64, budget_s=12.0, sweeps=5):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=10,
+                    help="timed solve chunks (0: only the hipEvent-timed plain launches)")
     ap.add_argument("--warmup", type=int, default=4,
                     help="untimed steps of the merit-checked solve that settle each graph's beta")
     ap.add_argument("--sweeps", type=int, default=50, help="sweeps per persistent launch (one step)")
@@ -228,6 +254,7 @@ def main():
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
+    ap.add_argument("--skip-chordal", action="store_true", help="skip the rotation-matrix model leg")
     ap.add_argument("--skip-ttt", action="store_true", help="skip the time-to-tolerance leg")
     ap.add_argument("--no-tune", action="store_true", help="use --schedule/--block as given")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phase", "graph"])
@@ -264,7 +291,7 @@ def main():
     epg = (eoff[1:] - eoff[:-1]).astype(np.int64)
     r32 = run_batch(P, torch, cat, voff, eoff, "fp32", betas, args.sweeps, args.steps, args.warmup,
                     tune, args.schedule, args.block, epg)
-    value = r32["edge_iters"] / r32["wall"]
+    value = r32["edge_iters"] / r32["wall"] if args.steps else None
     algo_bytes = (B_EDGE * m + B_VERTEX * n) * args.sweeps
     achieved = algo_bytes / (r32["kern_ms"] * 1e-3) / 1e9
     phase_bytes = (B_EDGE_PHASE * m + B_VERTEX_PHASE * n) * args.sweeps
@@ -273,7 +300,6 @@ def main():
     max_n = int(np.max(voff[1:] - voff[:-1]))
     kname = (("k_graph_sweeps_lds<float>" if 32 * max_n <= 160 * 1024 else "k_graph_sweeps<float>")
              if r32["info"]["schedule"] == 2 else "k_phase<*,float>")
-    F0, F1 = r32["F0"], r32["res"][:, 5]
     out = {
         "metric": "edge-iters/s + time to 1e-6 rel cost; FP32/batched vs plain FP64, 1 GPU",
         "value": value,
@@ -281,7 +307,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": r32["wall"] / args.steps * 1e3,
+        "ms_per_step": r32["wall"] / args.steps * 1e3 if args.steps else None,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -297,21 +323,38 @@ def main():
                      "bytes_per_launch": algo_bytes,
                      "bytes_model": f"{B_EDGE} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps",
                      "phase_model_GBs": phase_bytes / (r32["kern_ms"] * 1e-3) / 1e9},
-        "batch_health": {"graphs_cost_up": int(np.sum(~(F1 <= F0))),
-                         "median_final_over_initial": float(np.median(F1 / F0)),
-                         "worst_final_over_initial": float(np.max(F1 / F0)),
-                         "graphs_beta_raised": int(np.sum(r32["beta"] > betas)),
-                         "max_beta_over_initial": float(np.max(r32["beta"] / betas)),
-                         "sweeps_per_graph": int(r32["accepted"].max())},
+        "batch_health": health(r32, betas),
     }
     r64 = None
     if not args.skip_fp64:
-        steps64 = max(2, args.steps // 2)
+        steps64 = max(2, args.steps // 2) if args.steps else 0
         r64 = run_batch(P, torch, cat, voff, eoff, "fp64", betas, args.sweeps, steps64, args.warmup,
                         tune, args.schedule, args.block, epg)
-        v64 = r64["edge_iters"] / r64["wall"]
-        out["fp64"] = {"value": v64, "unit": "edge-iter/s", "kernel_ms_per_launch": r64["kern_ms"],
-                       "speedup_fp32_over_fp64": value / v64}
+        v64 = r64["edge_iters"] / r64["wall"] if steps64 else None
+        out["fp64"] = {"value": v64, "unit": "edge-iter/s", "steps": steps64,
+                       "kernel_ms_per_launch": r64["kern_ms"],
+                       "speedup_fp32_over_fp64": value / v64 if v64 else None,
+                       "kernel_speedup_fp32_over_fp64": r64["kern_ms"] / r32["kern_ms"],
+                       "batch_health": health(r64, betas)}
+    if not args.skip_chordal:
+        # the rotation-matrix rendering on the same batch (FP32): state
+        # P, Q, Lambda (9 words each), t, s, z; edges kappa R~ (9), tau t~, tau
+        stc = max(2, args.steps // 2) if args.steps else 0
+        rc = run_batch(P, torch, cat, voff, eoff, "fp32", betas, args.sweeps, stc,
+                       max(1, args.warmup // 2) if args.steps else 0, tune, args.schedule,
+                       args.block, epg, model="chordal")
+        cb = (B_EDGE_CHORDAL * m + B_VERTEX_CHORDAL * n) * args.sweeps
+        ca = cb / (rc["kern_ms"] * 1e-3) / 1e9
+        out["chordal"] = {
+            "value": rc["edge_iters"] / rc["wall"] if stc else None, "unit": "edge-iter/s",
+            "steps": stc, "dtype": "f32", "kernel": "k_graph_sweeps_c<float>"
+            if rc["info"]["schedule"] == 2 else "k_phase_c<*,float>",
+            "kernel_ms_per_launch": rc["kern_ms"],
+            "roofline": {"bound": "hbm", "achieved": ca, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ca / HBM_PEAK_GBS, "traffic": load_traffic("k_graph_sweeps_c<float>"),
+                         "bytes_model": f"{B_EDGE_CHORDAL} B/edge + {B_VERTEX_CHORDAL} B/pose per "
+                                        f"sweep x {args.sweeps} sweeps"},
+            "batch_health": health(rc, betas)}
     if not args.skip_ttt:
         F_star = converged_cost(P, g1k, beta1k)
         ttt = {"workload": "grid-1k", "F_star": F_star,
@@ -322,7 +365,7 @@ def main():
         if ttt["fp64"]["seconds"] and ttt["fp32"]["seconds"]:
             ttt["speedup_fp32_over_fp64"] = ttt["fp64"]["seconds"] / ttt["fp32"]["seconds"]
         out["time_to_1e-6"] = ttt
-    if not args.skip_cpu:
+    if not args.skip_cpu and args.steps:
         out["cpu_baseline"] = cpu_leg(batch, betas, voff, r32, r64)
     print(json.dumps(out), flush=True)
 
