@@ -295,10 +295,7 @@ def main():
     algo_bytes = (B_EDGE * m + B_VERTEX * n) * args.sweeps
     achieved = algo_bytes / (r32["kern_ms"] * 1e-3) / 1e9
     phase_bytes = (B_EDGE_PHASE * m + B_VERTEX_PHASE * n) * args.sweeps
-    # the per-graph kernel keeps lambda and z in LDS when 32 B x the largest
-    # graph's pose count fits in 160 KiB (FP32)
-    max_n = int(np.max(voff[1:] - voff[:-1]))
-    kname = (("k_graph_sweeps_lds<float>" if 32 * max_n <= 160 * 1024 else "k_graph_sweeps<float>")
+    kname = (("k_graph_sweeps_lds<float>" if r32["info"]["lds"] else "k_graph_sweeps<float>")
              if r32["info"]["schedule"] == 2 else "k_phase<*,float>")
     out = {
         "metric": "edge-iters/s + time to 1e-6 rel cost; FP32/batched vs plain FP64, 1 GPU",
@@ -316,7 +313,8 @@ def main():
         "config": {"workload": "batched-4096", "graphs": args.graphs, "poses": n, "edges": m,
                    "sweeps_per_step": args.sweeps, "beta": f"{BETA_SCALE} x mean diagonal weight, per graph",
                    "gamma": GAMMA, "schedule": ["auto", "phase", "graph"][r32["info"]["schedule"]],
-                   "block": r32["info"]["block"], "parallelism": "none (1 GPU)"},
+                   "block": r32["info"]["block"], "lds_multipliers": bool(r32["info"]["lds"]),
+                   "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname),
                      "kernel": kname, "kernel_ms_per_launch": r32["kern_ms"],

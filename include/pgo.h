@@ -188,8 +188,10 @@ pgo_status pgo_merit(pgo_graph* g, double* out);
  * launch per chunk for all graphs still running).  After each chunk, for
  * every running graph:
  *   - if beta_growth > 1 and its merit Psi (see pgo_merit) rose over the
- *     chunk by more than the rounding jitter of the state (1e-12 |Psi| in
- *     FP64, 1e-7 |Psi| in FP32), or the chunk left a non-finite value in
+ *     chunk by more than the rounding noise of the state (1e-12 |Psi| +
+ *     8 eps (beta + w) n, eps the unit roundoff of the precision, w the
+ *     graph's mean vertex weight 2 sum_out (tau |t~|^2 + kappa) + 2 sum_in
+ *     kappa, n its vertex count), or the chunk left a non-finite value in
  *     the graph, the chunk is undone for that graph (state restored on the
  *     device) and its beta multiplied by beta_growth (at most 40 times per
  *     call and never past 1e30; Theorem 1 asks beta above a threshold the
@@ -226,15 +228,19 @@ pgo_status pgo_set_state(pgo_graph* g, const double* state);
  * initial rotations P^0 (n x 9), row-major. */
 pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat0);
 
-/* Sizes and settings of the handle; any pointer may be NULL. */
+/* Sizes and settings of the handle; any pointer may be NULL.  lds = 1 when
+ * the per-graph schedule keeps every vertex's multipliers in LDS for the
+ * whole launch (quaternion model, 8 words x the largest graph's vertex
+ * count within 160 KiB, chosen by default or by the autotuner). */
 pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
-                    int32_t* schedule, int32_t* block, int32_t* model);
+                    int32_t* schedule, int32_t* block, int32_t* model, int32_t* lds);
 
 /*
- * pgo_autotune -- time the candidate schedules and workgroup sizes on this
- * handle's own graphs (sweeps sweeps each, beta, gamma), keep the fastest for
- * later pgo_iterate calls, and restore the state it found.  Reports the
- * chosen schedule and block size through pgo_info.
+ * pgo_autotune -- time the candidate schedules, workgroup sizes and (per-
+ * graph schedule) LDS residency of the multipliers on this handle's own
+ * graphs (sweeps sweeps each, beta, gamma), keep the fastest for later
+ * pgo_iterate calls, and restore the state it found.  Reports the choice
+ * through pgo_info.
  */
 pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps);
 

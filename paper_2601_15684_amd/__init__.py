@@ -69,7 +69,7 @@ _SIGNATURES = {
     "pgo_get_state": (C.c_int, [_P, _D]),
     "pgo_set_state": (C.c_int, [_P, _D]),
     "pgo_get_prepared": (C.c_int, [_P, _D, _D]),
-    "pgo_info": (C.c_int, [_P, _I64, _I64, _I32, _I32, _I32, _I32, _I32]),
+    "pgo_info": (C.c_int, [_P, _I64, _I64, _I32, _I32, _I32, _I32, _I32, _I32]),
     "pgo_autotune": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32]),
     "pgo_set_edge_params": (C.c_int, [_P, _P, _P, _P, _P]),
     "pgo_reset_state": (C.c_int, [_P]),
@@ -183,11 +183,12 @@ def pgo_iterate_graphs(h, k, beta, gamma):
 
 def pgo_info(h):
     n, m = C.c_int64(), C.c_int64()
-    G, prec, sched, block, model = (C.c_int32() for _ in range(5))
+    G, prec, sched, block, model, lds = (C.c_int32() for _ in range(6))
     _chk(lib().pgo_info(h, C.byref(n), C.byref(m), C.byref(G), C.byref(prec), C.byref(sched),
-                        C.byref(block), C.byref(model)))
+                        C.byref(block), C.byref(model), C.byref(lds)))
     return dict(n=n.value, m=m.value, G=G.value, precision=prec.value, schedule=sched.value,
-                block=block.value, model=model.value, width=STATE_WIDTH[model.value])
+                block=block.value, model=model.value, width=STATE_WIDTH[model.value],
+                lds=lds.value)
 
 
 def pgo_cost(h):

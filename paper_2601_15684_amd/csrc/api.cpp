@@ -57,6 +57,7 @@ struct pgo_graph {
   int32_t* gid = nullptr;           // graph of each vertex
   double* beta_dev = nullptr;       // per-graph penalties of the last pgo_iterate_graphs
   std::vector<double> beta_h;       // penalty of each graph in the last iterate call
+  std::vector<double> wbar_h;       // mean vertex weight of each graph (merit noise scale)
   double last_gamma = 1.0;
   int32_t* active_dev = nullptr;    // per-graph run flags (pgo_solve)
   int32_t* flag_dev = nullptr;      // per-graph restore flags (pgo_solve)
@@ -93,7 +94,7 @@ struct pgo_graph {
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
-  int graph_regs = 1;  // per-graph kernel keeps lambda and z in LDS when they fit
+  int graph_lds = 1;  // per-graph kernel keeps lambda and z in LDS when they fit
   bool have_prev = false;
   // captured launch sequence of the per-phase schedule
   hipGraphExec_t gexec = nullptr;
@@ -196,6 +197,13 @@ DevChordal<T> viewc(const pgo_graph* g) {
   d.s_prev = static_cast<P4<T>*>(g->s_prev);
   d.z_prev = static_cast<P4<T>*>(g->z_prev);
   return d;
+}
+
+// Whether the quaternion per-graph kernel can hold every vertex's lambda and
+// z in LDS (the rule of launch_graph_sweeps: (4 + 4) words x max_n <= 160 KiB).
+bool lds_fits(const pgo_graph* g) {
+  const size_t w = g->opt.precision == PGO_FP64 ? 8 : 4;
+  return !g->chordal && 8 * w * size_t(g->max_n) <= 160 * 1024;
 }
 
 // words of T per vertex of a rotation-like block (p, q, lambda and edge w)
@@ -420,6 +428,16 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   g->m = eoff[G];
   g->voff_h.assign(voff, voff + G + 1);
   g->eoff_h.assign(eoff, eoff + G + 1);
+  // mean over a graph's vertices of the diagonal weight 2 sum_out (tau |t~|^2
+  // + kappa) + 2 sum_in kappa: the size of one vertex's update direction
+  g->wbar_h.assign(size_t(G), 0.0);
+  for (int32_t k = 0; k < G; ++k) {
+    double w = 0.0;
+    for (int64_t e = eoff[k]; e < eoff[k + 1]; ++e)
+      w += 2.0 * tau[e] * (tm[3 * e] * tm[3 * e] + tm[3 * e + 1] * tm[3 * e + 1] +
+                           tm[3 * e + 2] * tm[3 * e + 2]) + 4.0 * kappa[e];
+    g->wbar_h[size_t(k)] = w / double(voff[k + 1] - voff[k]);
+  }
   for (int32_t k = 0; k < G; ++k) g->max_n = std::max<int32_t>(g->max_n, int32_t(voff[k + 1] - voff[k]));
   auto bail = [&](pgo_status st) {
     pgo_destroy(g);
@@ -565,7 +583,7 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
       HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->stream));
     else
       HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->max_n,
-                                    g->graph_regs, g->stream));
+                                    g->graph_lds, g->stream));
     return PGO_OK;
   }
   auto phases = [&](hipStream_t st) {
@@ -995,10 +1013,12 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
   const bool adapt = beta_growth > 1.0;
   constexpr int kMaxRejects = 40;
   constexpr double kBetaMax = 1e30;  // a penalty stays representable in FP32
-  // A chunk counts as a rise of the merit only beyond the rounding jitter of
-  // the state it is evaluated on: FP32 states move by a few ulps per sweep
-  // even at a fixed point, which shifts the merit by ~1e-9 relative.
-  const double mtol = g->opt.precision == PGO_FP32 ? 1e-7 : 1e-12;
+  // A chunk counts as a rise of the merit only beyond the rounding noise of
+  // the state it is evaluated on.  Rounding a stored rotation moves it off
+  // its manifold by a few ulps, which changes L_beta to first order by the
+  // size of the vertex's update direction, at most ~(beta + w) per vertex
+  // (w the mean diagonal weight): noise <= 8 eps (beta + w) n per graph.
+  const double eps = g->opt.precision == PGO_FP32 ? 0x1p-24 : 0x1p-53;
   std::vector<int32_t> active(size_t(G), 1), done(size_t(G), 0), conv(size_t(G), 0),
       rejects(size_t(G), 0), flags(size_t(G), 0);
   std::vector<double> r, r_acc;
@@ -1031,7 +1051,9 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
       double L1, psi1, L0, psi0;
       merit_of(v, beta[j], gamma, &L1, &psi1);
       merit_of(&r_acc[size_t(kRedVals) * j], beta[j], gamma, &L0, &psi0);
-      const bool rose = !finite || psi1 > psi0 + mtol * std::fabs(psi0);
+      const double ng = double(g->voff_h[size_t(j) + 1] - g->voff_h[size_t(j)]);
+      const double noise = 8.0 * eps * (beta[j] + g->wbar_h[size_t(j)]) * ng;
+      const bool rose = !finite || psi1 > psi0 + 1e-12 * std::fabs(psi0) + noise;
       const bool can_raise = rejects[size_t(j)] < kMaxRejects && beta[j] * beta_growth <= kBetaMax;
       if (!finite && !(adapt && can_raise))
         return fail(PGO_ENUMERIC, "graph " + std::to_string(j) +
@@ -1154,7 +1176,7 @@ pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat
 }
 
 pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
-                    int32_t* schedule, int32_t* block, int32_t* model) {
+                    int32_t* schedule, int32_t* block, int32_t* model, int32_t* lds) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
   if (n) *n = g->n;
   if (m) *m = g->m;
@@ -1163,6 +1185,7 @@ pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* p
   if (schedule) *schedule = g->sched;
   if (block) *block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
   if (model) *model = g->opt.model;
+  if (lds) *lds = (g->sched == PGO_SCHED_GRAPH && g->graph_lds && lds_fits(g)) ? 1 : 0;
   return PGO_OK;
 }
 
@@ -1176,18 +1199,24 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
   pgo_status s = pgo_get_state(g, saved.data());
   if (s != PGO_OK) return s;
   struct Cand {
-    int sched, block;
+    int sched, block, lds;
   };
   std::vector<Cand> cands;
-  for (int b : {64, 128, 256, 512}) cands.push_back({PGO_SCHED_PHASE, b});
+  for (int b : {64, 128, 256, 512}) cands.push_back({PGO_SCHED_PHASE, b, 0});
   if (g->max_n <= PGO_GRAPH_SCHED_MAX_N)
-    for (int b : {128, 256, 512, 1024}) cands.push_back({PGO_SCHED_GRAPH, b});
+    for (int b : {128, 256, 512, 1024}) {
+      cands.push_back({PGO_SCHED_GRAPH, b, 0});
+      if (lds_fits(g)) cands.push_back({PGO_SCHED_GRAPH, b, 1});
+    }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  Cand pick{g->sched, g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase};
+  Cand pick{g->sched, g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase,
+            g->graph_lds};
+  const int lds_before = g->graph_lds;
   for (const Cand& c : cands) {
+    g->graph_lds = c.lds;
     if ((s = pgo_set_state(g, saved.data())) != PGO_OK) break;
     if ((s = iterate_with(g, sweeps, beta, gamma, c.sched, c.block)) != PGO_OK) break;  // warm-up
     if ((s = pgo_set_state(g, saved.data())) != PGO_OK) break;
@@ -1204,8 +1233,10 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  g->graph_lds = lds_before;
   if (s != PGO_OK) return s;
   g->sched = pick.sched;
+  if (pick.sched == PGO_SCHED_GRAPH) g->graph_lds = pick.lds;
   if (pick.sched == PGO_SCHED_GRAPH)
     g->block_graph = pick.block;
   else

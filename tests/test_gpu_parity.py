@@ -298,3 +298,23 @@ def test_full_size_grid_100k_parity(pgo):
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
         got, _, _ = gpu_run(pgo, g, 10, beta, precision=prec, schedule="phase")
         assert_parity(scaled_err(got, ref, beta), tol, f"grid-100k/{prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replays_equal_eager_launches(pgo, prec):
+    """The per-phase schedule captures a k-sweep call into a HIP graph once
+    and replays it: three replays from the same state, with eager library
+    work (reductions, state transfers) and synchronisations in between, each
+    equal bit for bit to k single-sweep (uncaptured) calls."""
+    g = S.make_config("sphere-2.5k")
+    beta = 0.01 * abar(g)
+    with pgo.PoseGraph.from_graph(g, precision=prec, schedule="phase") as h:
+        s0 = h.state()
+        for _ in range(5):
+            h.iterate(1, beta, GAMMA)
+        eager = h.state()
+        for _ in range(3):
+            h.set_state(s0)
+            h.iterate(5, beta, GAMMA)
+            h.cost()
+            assert np.array_equal(h.state(), eager)
