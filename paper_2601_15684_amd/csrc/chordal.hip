@@ -74,29 +74,37 @@ __device__ void p_matrix(const DevChordal<T>& g, int i, const SweepParams& sp, c
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = A(0);
   const A sx = A(si_.x), sy = A(si_.y), sz = A(si_.z);
-  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
-    const P4<T> tj = g.t[g.o_nbr[e]];
-    const P4<T> u = g.o_tt[e];
-    const A d[3] = {A(tj.x) - sx, A(tj.y) - sy, A(tj.z) - sz};
-    const A uu[3] = {A(u.x), A(u.y), A(u.z)};
+  struct OutE {
+    P4<T> tj, u;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
+      [&](const OutE& x) {
+        const A d[3] = {A(x.tj.x) - sx, A(x.tj.y) - sy, A(x.tj.z) - sz};
+        const A uu[3] = {A(x.u.x), A(x.u.y), A(x.u.z)};
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc[3 * r + c] += d[r] * uu[c];
-    if (kMag)
-      mag += (fabs(d[0]) + fabs(d[1]) + fabs(d[2])) * (fabs(uu[0]) + fabs(uu[1]) + fabs(uu[2]));
-  }
-  for (int e = g.i_ptr[i]; e < g.i_ptr[i + 1]; ++e) {
-    A Ql[9], W[9];
-    ld9<A>(g.Q[g.i_nbr[e]], Ql);
-    ld9<A>(g.i_R[e], W);
+          for (int c = 0; c < 3; ++c) acc[3 * r + c] += d[r] * uu[c];
+        if (kMag)
+          mag += (fabs(d[0]) + fabs(d[1]) + fabs(d[2])) * (fabs(uu[0]) + fabs(uu[1]) + fabs(uu[2]));
+      });
+  struct InE {
+    R3<T> Ql, W;
+  };
+  edge_loop<1>(  // two 3x3 pairs in flight would spill registers
+      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{g.Q[g.i_nbr[e]], g.i_R[e]}; },
+      [&](const InE& x) {
+        A Ql[9], W[9];
+        ld9<A>(x.Ql, Ql);
+        ld9<A>(x.W, W);
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-        acc[3 * r + c] += Ql[3 * r] * W[c] + Ql[3 * r + 1] * W[3 + c] + Ql[3 * r + 2] * W[6 + c];
-    if (kMag) mag += l1_9(Ql) * l1_9(W);
-  }
+          for (int c = 0; c < 3; ++c)
+            acc[3 * r + c] += Ql[3 * r] * W[c] + Ql[3 * r + 1] * W[3 + c] + Ql[3 * r + 2] * W[6 + c];
+        if (kMag) mag += l1_9(Ql) * l1_9(W);
+      });
   A Qi[9], Pi[9], Li[9];
   ld9<A>(Qi_, Qi);
   ld9<A>(Pi_, Pi);
@@ -143,17 +151,22 @@ __device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, int i, const Sw
   T acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = T(0);
-  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
-    T Pj[9], W[9];
-    ld9<T>(g.P[g.o_nbr[e]], Pj);
-    ld9<T>(g.o_R[e], W);
+  struct OutE {
+    R3<T> Pj, W;
+  };
+  edge_loop<1>(
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.P[g.o_nbr[e]], g.o_R[e]}; },
+      [&](const OutE& x) {
+        T Pj[9], W[9];
+        ld9<T>(x.Pj, Pj);
+        ld9<T>(x.W, W);
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+        for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int c = 0; c < 3; ++c)  // (P_j W^T)[r][c] = sum_k P_j[r][k] W[c][k]
-        acc[3 * r + c] += Pj[3 * r] * W[3 * c] + Pj[3 * r + 1] * W[3 * c + 1] +
-                          Pj[3 * r + 2] * W[3 * c + 2];
-  }
+          for (int c = 0; c < 3; ++c)  // (P_j W^T)[r][c] = sum_k P_j[r][k] W[c][k]
+            acc[3 * r + c] += Pj[3 * r] * W[3 * c] + Pj[3 * r + 1] * W[3 * c + 1] +
+                              Pj[3 * r + 2] * W[3 * c + 2];
+      });
   T Pi[9], Qi[9], Li[9], Qn[9], Ln[9];
   const R3<T> Qold = g.Q[i];
   ld9<T>(g.P[i], Pi);
@@ -186,15 +199,22 @@ template <typename T>
 __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, int i, const SweepParams& sp,
                                          bool save, const V3<T>& zi, T cT) {
   V3<T> acc = {T(0), T(0), T(0)};
-  for (int e = g.i_ptr[i]; e < g.i_ptr[i + 1]; ++e) {
-    const int l = g.i_nbr[e];
-    const P4<T> u = g.i_tt[e];
-    const P4<T> sl = g.s[l];
-    const V3<T> c = mat_vec(g.P[l], u);  // P_l (tau t~)
-    acc.x += u.u * sl.x + c.x;
-    acc.y += u.u * sl.y + c.y;
-    acc.z += u.u * sl.z + c.z;
-  }
+  struct InE {
+    P4<T> u, sl;
+    R3<T> Pl;
+  };
+  edge_loop(
+      g.i_ptr[i], g.i_ptr[i + 1],
+      [&](int e) {
+        const int l = g.i_nbr[e];
+        return InE{g.i_tt[e], g.s[l], g.P[l]};
+      },
+      [&](const InE& x) {
+        const V3<T> c = mat_vec(x.Pl, x.u);  // P_l (tau t~)
+        acc.x += x.u.u * x.sl.x + c.x;
+        acc.y += x.u.u * x.sl.y + c.y;
+        acc.z += x.u.u * x.sl.z + c.z;
+      });
   const P4<T> ti = g.t[i], si = g.s[i];
   const T b = T(sp.beta), h = T(sp.h3);
   const T a = cT + b + h;
@@ -210,14 +230,17 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const Sw
                                          R3<T>* Q_out = nullptr, P4<T>* s_out = nullptr) {
   const R3<T> Pi = g.P[i];
   V3<T> acc = {T(0), T(0), T(0)};
-  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
-    const P4<T> u = g.o_tt[e];
-    const P4<T> tj = g.t[g.o_nbr[e]];
-    const V3<T> c = mat_vec(Pi, u);  // P_i (tau t~)
-    acc.x += u.u * tj.x - c.x;
-    acc.y += u.u * tj.y - c.y;
-    acc.z += u.u * tj.z - c.z;
-  }
+  struct OutE {
+    P4<T> u, tj;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]]}; },
+      [&](const OutE& x) {
+        const V3<T> c = mat_vec(Pi, x.u);  // P_i (tau t~)
+        acc.x += x.u.u * x.tj.x - c.x;
+        acc.y += x.u.u * x.tj.y - c.y;
+        acc.z += x.u.u * x.tj.z - c.z;
+      });
   const P4<T> ti = g.t[i], si = g.s[i];
   const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);

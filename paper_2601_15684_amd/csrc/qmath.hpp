@@ -92,4 +92,28 @@ __device__ __forceinline__ Q4<T> cvt(const Q4<U>& a) {
   return {T(a.w), T(a.x), T(a.y), T(a.z)};
 }
 
+#ifndef PGO_EDGE_UNROLL
+#define PGO_EDGE_UNROLL 2
+#endif
+
+// Visits the edges [e0, e1) of one vertex in order.  load(e) issues the
+// edge's loads (its record and the neighbour gathers it indexes), use(d)
+// does its arithmetic.  U edges are loaded before any is used, so U chains
+// of index-then-gather are in flight at once per thread; use runs in edge
+// order, so every sum is the same as one edge at a time.
+template <int U = PGO_EDGE_UNROLL, typename Load, typename Use>
+__device__ __forceinline__ void edge_loop(int e0, int e1, Load&& load, Use&& use) {
+  int e = e0;
+  if (U > 1) {
+    for (; e + U <= e1; e += U) {
+      decltype(load(e)) d[U];
+#pragma unroll
+      for (int k = 0; k < U; ++k) d[k] = load(e + k);
+#pragma unroll
+      for (int k = 0; k < U; ++k) use(d[k]);
+    }
+  }
+  for (; e < e1; ++e) use(load(e));
+}
+
 }  // namespace pgo

@@ -55,23 +55,29 @@ __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, const Q
   const Q4<A> qi = cvt<A>(q_i);
   const V3<A> si = v3a<A>(s_i);
   Q4<A> acc = {A(0), A(0), A(0), A(0)};
-  const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
-  for (int e = o0; e < o1; ++e) {
-    const int j = g.o_nbr[e];
-    const V3<A> tj = v3a<A>(g.t[j]);
-    const V3<A> u = v3a<A>(g.o_tt[e]);
-    const V3<A> mr = {si.x - tj.x, si.y - tj.y, si.z - tj.z};  // [0, r]^* = [0, s_i - t_j]
-    const Q4<A> term = qmul_vp(qmul_pv(mr, qi), u);
-    acc4(acc, term);
-    if (kMag) mag += l1(term);
-  }
-  const int n0 = g.i_ptr[i], n1 = g.i_ptr[i + 1];
-  for (int e = n0; e < n1; ++e) {
-    const int l = g.i_nbr[e];
-    const Q4<A> term = qmul(cvt<A>(g.q[l]), cvt<A>(g.i_w[e]));
-    acc4(acc, term);
-    if (kMag) mag += l1(term);
-  }
+  struct OutE {
+    P4<T> tj, u;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
+      [&](const OutE& d) {
+        const V3<A> tj = v3a<A>(d.tj);
+        const V3<A> u = v3a<A>(d.u);
+        const V3<A> mr = {si.x - tj.x, si.y - tj.y, si.z - tj.z};  // [0, r]^* = [0, s_i - t_j]
+        const Q4<A> term = qmul_vp(qmul_pv(mr, qi), u);
+        acc4(acc, term);
+        if (kMag) mag += l1(term);
+      });
+  struct InE {
+    Q4<T> ql, w;
+  };
+  edge_loop(
+      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{g.q[g.i_nbr[e]], g.i_w[e]}; },
+      [&](const InE& d) {
+        const Q4<A> term = qmul(cvt<A>(d.ql), cvt<A>(d.w));
+        acc4(acc, term);
+        if (kMag) mag += l1(term);
+      });
   return acc;
 }
 
@@ -127,16 +133,23 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const Swee
   const Q4<T> pi = g.p[i], qi = g.q[i], li = lam;
   const V3<T> si = v3(g.s[i]);
   Q4<T> acc = {T(0), T(0), T(0), T(0)};
-  const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
-  for (int e = o0; e < o1; ++e) {
-    const int j = g.o_nbr[e];
-    const V3<T> tj = v3(g.t[j]);
-    const P4<T> u = g.o_tt[e];
-    const V3<T> r = {tj.x - si.x, tj.y - si.y, tj.z - si.z};
-    const V3<T> mu = {-u.x, -u.y, -u.z};  // [0, tau t~]^*
-    acc4(acc, qmul_vp(qmul_pv(r, pi), mu));
-    acc4(acc, qmul(g.p[j], qconj(g.o_w[e])));
-  }
+  struct OutE {
+    P4<T> tj, u;
+    Q4<T> pj, w;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1],
+      [&](int e) {
+        const int j = g.o_nbr[e];
+        return OutE{g.t[j], g.o_tt[e], g.p[j], g.o_w[e]};
+      },
+      [&](const OutE& d) {
+        const V3<T> tj = v3(d.tj);
+        const V3<T> r = {tj.x - si.x, tj.y - si.y, tj.z - si.z};
+        const V3<T> mu = {-d.u.x, -d.u.y, -d.u.z};  // [0, tau t~]^*
+        acc4(acc, qmul_vp(qmul_pv(r, pi), mu));
+        acc4(acc, qmul(d.pj, qconj(d.w)));
+      });
   const T b = T(sp.beta), h = T(sp.h2);
   const T a = cQ + b + h;
   const Q4<T> qn = {(T(2) * acc.w + b * pi.w - li.w + h * qi.w) / a,
@@ -157,16 +170,22 @@ template <typename T>
 __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const SweepParams& sp,
                                          bool save, const V3<T>& zi, T cT) {
   V3<T> acc = {T(0), T(0), T(0)};
-  const int n0 = g.i_ptr[i], n1 = g.i_ptr[i + 1];
-  for (int e = n0; e < n1; ++e) {
-    const int l = g.i_nbr[e];
-    const P4<T> u = g.i_tt[e];
-    const V3<T> sl = v3(g.s[l]);
-    const V3<T> c = im_mul_conj(qmul_vp(g.q[l], v3(u)), g.p[l]);  // Im(q_l [0,tau t~] p_l^*)
-    acc.x += u.u * sl.x + c.x;
-    acc.y += u.u * sl.y + c.y;
-    acc.z += u.u * sl.z + c.z;
-  }
+  struct InE {
+    P4<T> u, sl;
+    Q4<T> ql, pl;
+  };
+  edge_loop(
+      g.i_ptr[i], g.i_ptr[i + 1],
+      [&](int e) {
+        const int l = g.i_nbr[e];
+        return InE{g.i_tt[e], g.s[l], g.q[l], g.p[l]};
+      },
+      [&](const InE& d) {
+        const V3<T> c = im_mul_conj(qmul_vp(d.ql, v3(d.u)), d.pl);  // Im(q_l [0,tau t~] p_l^*)
+        acc.x += d.u.u * d.sl.x + c.x;
+        acc.y += d.u.u * d.sl.y + c.y;
+        acc.z += d.u.u * d.sl.z + c.z;
+      });
   const P4<T> ti = g.t[i], si = g.s[i];
   const T b = T(sp.beta), h = T(sp.h3);
   const T a = cT + b + h;
@@ -182,16 +201,17 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
                                          Q4<T>* q_out = nullptr, P4<T>* s_out = nullptr) {
   const Q4<T> pi = g.p[i], qi = g.q[i];
   V3<T> acc = {T(0), T(0), T(0)};
-  const int o0 = g.o_ptr[i], o1 = g.o_ptr[i + 1];
-  for (int e = o0; e < o1; ++e) {
-    const int j = g.o_nbr[e];
-    const P4<T> u = g.o_tt[e];
-    const V3<T> tj = v3(g.t[j]);
-    const V3<T> c = im_mul_conj(qmul_vp(qi, v3(u)), pi);  // Im(q_i [0,tau t~] p_i^*)
-    acc.x += u.u * tj.x - c.x;
-    acc.y += u.u * tj.y - c.y;
-    acc.z += u.u * tj.z - c.z;
-  }
+  struct OutE {
+    P4<T> u, tj;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]]}; },
+      [&](const OutE& d) {
+        const V3<T> c = im_mul_conj(qmul_vp(qi, v3(d.u)), pi);  // Im(q_i [0,tau t~] p_i^*)
+        acc.x += d.u.u * d.tj.x - c.x;
+        acc.y += d.u.u * d.tj.y - c.y;
+        acc.z += d.u.u * d.tj.z - c.z;
+      });
   const P4<T> ti = g.t[i], si = g.s[i];
   const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);
