@@ -245,6 +245,29 @@ pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* p
 pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps);
 
 /*
+ * pgo_chordal_init -- chordal initialisation, the step before the path (the
+ * experiments section starts every method from it; the paper cites it
+ * without describing it).  Per graph and connected component, with the
+ * component's lowest-index vertex held at its current initial pose:
+ *   1. relaxed rotations: min sum_e kappa_e |R_i R~_e - R_j|_F^2 over free
+ *      3x3 blocks (model (1)'s rotation term in chordal distance, App. A.4);
+ *   2. each R_i projected onto SO(3) (3x3 polar factor);
+ *   3. translations: min sum_e tau_e |t_j - t_i - R_i t~_e|^2.
+ * Both least-squares problems are solved on the device in FP64 by
+ * Jacobi-preconditioned conjugate gradients per graph, from the current
+ * initial point, until <r, M^-1 r> <= tol^2 of its starting value or
+ * max_iters iterations.  The result replaces the handle's initial point
+ * (quaternion model: p^0 and the sign alignment of every edge, R7) and the
+ * state is reset to it (as pgo_reset_state).
+ *   max_iters >= 1; tol in (0, 1)
+ *   iters  out, G x 2 (iterations of the rotation and translation solves),
+ *          may be NULL
+ * Device scratch is allocated for the call and released before it returns.
+ * Synchronises the stream.
+ */
+pgo_status pgo_chordal_init(pgo_graph* g, int32_t max_iters, double tol, int32_t* iters);
+
+/*
  * Differentiation of K unrolled sweeps (reverse mode written by hand).
  * pgo_set_edge_params, pgo_forward_record and pgo_adjoint exist for the
  * quaternion model only (PGO_ESTATE on a chordal handle).

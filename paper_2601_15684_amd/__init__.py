@@ -18,7 +18,7 @@ __all__ = [
     "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
-    "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint",
+    "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint", "pgo_chordal_init",
     "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "MODEL_QUAT", "MODEL_CHORDAL",
     "LIB_PATH", "split_state",
 ]
@@ -76,6 +76,7 @@ _SIGNATURES = {
     "pgo_get_state_dev": (C.c_int, [_P, _P]),
     "pgo_forward_record": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32]),
     "pgo_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
+    "pgo_chordal_init": (C.c_int, [_P, C.c_int32, C.c_double, _I32]),
     "pgo_destroy": (None, [_P]),
     "pgo_last_error": (C.c_char_p, []),
 }
@@ -282,6 +283,14 @@ def pgo_adjoint(h, dL_dstate_dev, g_kappa=0, g_tau=0, g_tm=0, g_omega=0, dL_dsta
                            _vp(g_omega), _vp(dL_dstate0)))
 
 
+def pgo_chordal_init(h, max_iters=2000, tol=1e-12):
+    """Returns the (G, 2) iteration counts of the rotation and translation solves."""
+    G = pgo_info(h)["G"]
+    its = np.zeros((G, 2), np.int32)
+    _chk(lib().pgo_chordal_init(h, int(max_iters), float(tol), _ip(its)))
+    return its
+
+
 def pgo_destroy(h):
     if h:
         lib().pgo_destroy(h)
@@ -355,6 +364,9 @@ class PoseGraph:
 
     def set_stream(self, stream):
         pgo_set_stream(self.h, stream)
+
+    def chordal_init(self, max_iters=2000, tol=1e-12):
+        return pgo_chordal_init(self.h, max_iters, tol)
 
     def close(self):
         if self.h:

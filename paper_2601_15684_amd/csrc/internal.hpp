@@ -168,6 +168,59 @@ hipError_t launch_restore_words(int32_t n, const int32_t* gid, const int32_t* fl
                                 void* const* dst, const void* const* src, const int* words,
                                 hipStream_t st);
 
+// Chordal initialisation (cinit.hip): FP64 preconditioned conjugate
+// gradients per graph on the relaxed rotation and the translation normal
+// equations.  Edge arrays in caller order, reached through the CSR/CSC
+// permutations.
+struct CinitGraph {
+  const int32_t* o_ptr;
+  const int32_t* o_nbr;
+  const int32_t* o_perm;
+  const int32_t* i_ptr;
+  const int32_t* i_nbr;
+  const int32_t* i_perm;
+  const double* wt;       // kappa (rotations) or tau (translations)
+  const double* R9;       // measured rotations, m x 9 row-major
+  const double* tm;       // m x 3
+  double* diag;           // n: sum of the weights at each vertex
+  const uint8_t* anchor;  // n: 1 = held at its given value
+};
+struct CinitVec {  // W doubles per vertex each
+  double* x;
+  double* r;
+  double* z;
+  double* p;
+  double* ap;
+};
+struct CinitChunks {  // vertex chunks, never straddling graphs
+  const int64_t* beg;
+  const int64_t* end;
+  const int32_t* cgraph;  // graph of each chunk
+  const int32_t* g_off;   // chunks of graph g: [g_off[g], g_off[g+1])
+  int n_chunks;
+  double* part;           // one partial per chunk
+};
+struct CinitScalars {  // one per graph
+  double* rz0;
+  double* rz;
+  double* alpha;
+  double* beta;
+  int32_t* active;
+  int32_t* iters;
+};
+hipError_t launch_cinit_diag(const CinitGraph& c, int32_t n, hipStream_t st);
+hipError_t launch_cinit_rhs_t(const CinitGraph& c, int32_t n, const double* R, double* rhs,
+                              hipStream_t st);
+hipError_t launch_cinit_project(int32_t n, const uint8_t* anchor, const double* X,
+                                const double* given, double* R, hipStream_t st);
+hipError_t launch_cinit_qmat(int64_t m, const Q4<double>* q, double* R, hipStream_t st);
+// Solves A x = b (b null: 0) for every graph, from the x given, W = 9 or 3;
+// stops a graph when <r, z> <= tol^2 <r0, z0> or after max_iters; checks
+// for global completion on the host every check_every iterations.
+hipError_t launch_cinit_cg(const CinitGraph& c, const CinitVec& v, const CinitChunks& ch, int W,
+                           const double* b, int max_iters, int check_every, double tol,
+                           const CinitScalars& s, int G, int32_t* host_active, hipStream_t st);
+
 // FP64 reductions (reduce.hip).  Items are split into chunks that never cross
 // a graph boundary; chunk c covers [cbeg[c], cend[c]) of graph cgraph[c].
 // Partial sums of a chunk are reduced in a fixed order, then each graph sums
