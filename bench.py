@@ -154,6 +154,27 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
                 state=state, accepted=accepted, edge_iters=edge_iters, beta=beta)
 
 
+def cinit_leg(P, torch, cat, voff, eoff, steps):
+    """Chordal initialisation of the whole batch on the device (FP64 CG per
+    graph, tolerance 1e-10): wall time of the call, iterations, and the cost
+    of the new initial point against the odometry start."""
+    opt = P.pgo_default_options(precision="fp32")
+    h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
+                             cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], cat["tau"], opt)
+    F_odo = P.pgo_cost(h)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = P.pgo_chordal_init(h, 4000, 1e-10)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    F_ch = P.pgo_cost(h)
+    P.pgo_destroy(h)
+    return {"workload": "batched-4096", "seconds": sec, "tol": 1e-10,
+            "iterations_max": [int(its[:, 0].max()), int(its[:, 1].max())],
+            "iterations_median": [float(np.median(its[:, 0])), float(np.median(its[:, 1]))],
+            "median_cost_chordal_over_odometry": float(np.median(F_ch / F_odo))}
+
+
 def health(r, betas):
     F0, F1 = r["F0"], r["res"][:, 5]
     return {"graphs_cost_up": int(np.sum(~(F1 <= F0))),
@@ -255,6 +276,7 @@ def main():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-chordal", action="store_true", help="skip the rotation-matrix model leg")
+    ap.add_argument("--skip-cinit", action="store_true", help="skip the chordal-initialisation leg")
     ap.add_argument("--skip-ttt", action="store_true", help="skip the time-to-tolerance leg")
     ap.add_argument("--no-tune", action="store_true", help="use --schedule/--block as given")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phase", "graph"])
@@ -353,6 +375,8 @@ def main():
                          "bytes_model": f"{B_EDGE_CHORDAL} B/edge + {B_VERTEX_CHORDAL} B/pose per "
                                         f"sweep x {args.sweeps} sweeps"},
             "batch_health": health(rc, betas)}
+    if not args.skip_cinit:
+        out["chordal_init"] = cinit_leg(P, torch, cat, voff, eoff, args.steps)
     if not args.skip_ttt:
         F_star = converged_cost(P, g1k, beta1k)
         ttt = {"workload": "grid-1k", "F_star": F_star,
