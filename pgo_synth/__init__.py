@@ -470,3 +470,13 @@ def make_config(name, seed=0, **kw):
     if name == "diff-20k":
         return grid(20, 25, 40, all_pairs=True, sigma_R=0.05, sigma_t=0.1, seed=seed, **kw)
     raise KeyError(name)
+
+
+def random_info(m, tau, aniso, seed=0):
+    """Per-edge 3x3 translation information matrices S_e = tau_e R diag(a) R^T
+    with random orientation R and eigenvalue ratios up to `aniso` (for the
+    general-Sigma workloads); shape (m, 3, 3), symmetric positive definite."""
+    rng = np.random.default_rng(seed)
+    R = so3_exp(rng.standard_normal((m, 3)))
+    a = np.exp(rng.uniform(-0.5, 0.5, (m, 3)) * np.log(aniso))
+    return np.asarray(tau, np.float64)[:, None, None] * (R * a[:, None, :]) @ np.transpose(R, (0, 2, 1))
