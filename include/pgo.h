@@ -78,10 +78,13 @@ typedef enum {
 
 typedef enum {
   PGO_MODEL_QUAT = 0,    /* the paper's unit-quaternion model (eq. 1-2) */
-  PGO_MODEL_CHORDAL = 1  /* rotation matrices, chordal rotation cost; FP32
+  PGO_MODEL_CHORDAL = 1, /* rotation matrices, chordal rotation cost; FP32
                             takes the P update's 3x3 polar factor in double
                             when it is ill-conditioned (sigma_2 + sign(det)
                             sigma_3 below 1e-2 of the summed term sizes) */
+  PGO_MODEL_QUAT_INFO = 2 /* the quaternion model with a full 3x3 translation
+                            information matrix per edge (pgo_create_info);
+                            at most 256 threads per workgroup */
 } pgo_model;
 
 typedef struct {
@@ -136,6 +139,25 @@ pgo_status pgo_create_batched(pgo_graph** out, int32_t G, const int64_t* voff,
                               const int32_t* ei, const int32_t* ej, const double* Rm,
                               const double* tm, const double* kappa, const double* tau,
                               const pgo_options* opt);
+
+/*
+ * pgo_create_info -- the quaternion model with a general translation weight
+ * per edge (Model section: Sigma1 = diag(c, Omega1^{-1}), Sigma2 = kappa I):
+ * info (m x 9, row-major) holds each edge's information matrix S_e =
+ * Omega_e^{-1}, symmetric (to 1e-12 of its largest entry) and positive
+ * definite; c_e = trace(S_e) / 3 (c is arbitrary in the paper; with S_e =
+ * tau_e I this is the isotropic model with tau_e).  The blocks of App. B are
+ * full matrices: the p update is the sphere-constrained quadratic of Lemma 1
+ * (solved per vertex in FP64 by the secular equation of Lemma B.1, hard case
+ * included), q a 4x4 and t, s 3x3 positive definite solves.  Other arrays
+ * and offsets as pgo_create_batched (G >= 1); opt->model is set to
+ * PGO_MODEL_QUAT_INFO.  The state is the quaternion model's (21 doubles).
+ * pgo_chordal_init weighs translations by c_e.  No reverse mode.
+ */
+pgo_status pgo_create_info(pgo_graph** out, int32_t G, const int64_t* voff, const int64_t* eoff,
+                           const double* R0, const double* t0, const int32_t* ei,
+                           const int32_t* ej, const double* Rm, const double* tm,
+                           const double* kappa, const double* info, const pgo_options* opt);
 
 /* Use the given hipStream_t (e.g. torch.cuda.current_stream().cuda_stream)
  * for all later work of the handle; NULL returns to the handle's own stream. */
@@ -270,7 +292,7 @@ pgo_status pgo_chordal_init(pgo_graph* g, int32_t max_iters, double tol, int32_t
 /*
  * Differentiation of K unrolled sweeps (reverse mode written by hand).
  * pgo_set_edge_params, pgo_forward_record and pgo_adjoint exist for the
- * quaternion model only (PGO_ESTATE on a chordal handle).
+ * isotropic quaternion model only (PGO_ESTATE on other handles).
  *
  * pgo_set_edge_params -- replace edge parameters in place (caller edge
  * order, device FP64 pointers; NULL keeps the current values): kappa (m),

@@ -20,14 +20,15 @@ __all__ = [
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
     "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint", "pgo_chordal_init",
     "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "MODEL_QUAT", "MODEL_CHORDAL",
+    "MODEL_QUAT_INFO", "pgo_create_info",
     "LIB_PATH", "split_state",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpgo.so")
 FP64, FP32 = 0, 1
 SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH = 0, 1, 2
-MODEL_QUAT, MODEL_CHORDAL = 0, 1
-STATE_WIDTH = {MODEL_QUAT: 21, MODEL_CHORDAL: 36}
+MODEL_QUAT, MODEL_CHORDAL, MODEL_QUAT_INFO = 0, 1, 2
+STATE_WIDTH = {MODEL_QUAT: 21, MODEL_CHORDAL: 36, MODEL_QUAT_INFO: 21}
 STATUS = {0: "PGO_OK", 1: "PGO_EINVAL", 2: "PGO_ENOMEM", 3: "PGO_EDEVICE", 4: "PGO_ENUMERIC",
           5: "PGO_ESTATE"}
 
@@ -57,6 +58,8 @@ _SIGNATURES = {
                              C.POINTER(PgoOptions)]),
     "pgo_create_batched": (C.c_int, [C.POINTER(_P), C.c_int32, _I64, _I64, _D, _D, _I32, _I32, _D, _D,
                                      _D, _D, C.POINTER(PgoOptions)]),
+    "pgo_create_info": (C.c_int, [C.POINTER(_P), C.c_int32, _I64, _I64, _D, _D, _I32, _I32, _D, _D,
+                                  _D, _D, C.POINTER(PgoOptions)]),
     "pgo_set_stream": (C.c_int, [_P, _P]),
     "pgo_iterate": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double]),
     "pgo_iterate_graphs": (C.c_int, [_P, C.c_int32, _D, C.c_double]),
@@ -137,7 +140,7 @@ def pgo_default_options(**kw) -> PgoOptions:
         elif k == "schedule" and isinstance(v, str):
             o.schedule = {"auto": SCHED_AUTO, "phase": SCHED_PHASE, "graph": SCHED_GRAPH}[v]
         elif k == "model" and isinstance(v, str):
-            o.model = {"quat": MODEL_QUAT, "chordal": MODEL_CHORDAL}[v]
+            o.model = {"quat": MODEL_QUAT, "chordal": MODEL_CHORDAL, "info": MODEL_QUAT_INFO}[v]
         else:
             setattr(o, k, v)
     return o
@@ -163,6 +166,21 @@ def pgo_create_batched(voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, tau, options=N
                                   _ip(arrs[2]), _ip(arrs[3]), _dp(arrs[4]), _dp(arrs[5]),
                                   _dp(arrs[6]), _dp(arrs[7]),
                                   C.byref(options) if options is not None else None))
+    return h
+
+
+def pgo_create_info(voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, info, options=None):
+    """The quaternion model with a 3x3 translation information matrix per edge
+    (info: m x 3 x 3 or m x 9)."""
+    voff = np.ascontiguousarray(voff, dtype=np.int64)
+    eoff = np.ascontiguousarray(eoff, dtype=np.int64)
+    arrs = [_f64(R0), _f64(t0), _i32(ei), _i32(ej), _f64(Rm), _f64(tm), _f64(kappa),
+            _f64(info).reshape(-1, 9)]
+    h = _P()
+    _chk(lib().pgo_create_info(C.byref(h), int(voff.shape[0] - 1), voff.ctypes.data_as(_I64),
+                               eoff.ctypes.data_as(_I64), _dp(arrs[0]), _dp(arrs[1]), _ip(arrs[2]),
+                               _ip(arrs[3]), _dp(arrs[4]), _dp(arrs[5]), _dp(arrs[6]), _dp(arrs[7]),
+                               C.byref(options) if options is not None else None))
     return h
 
 
@@ -314,14 +332,23 @@ class PoseGraph:
         self.h = handle
 
     @classmethod
-    def from_graph(cls, g, **opt):
+    def from_graph(cls, g, info=None, **opt):
+        """info (m x 3 x 3): per-edge translation information (information model)."""
+        if info is not None:
+            return cls(pgo_create_info([0, g.n], [0, g.m], g.R0.reshape(-1, 9), g.t0, g.ei, g.ej,
+                                       g.Rm.reshape(-1, 9), g.tm, g.kappa, info,
+                                       pgo_default_options(**opt)))
         return cls(pgo_create(g.n, g.R0.reshape(-1, 9), g.t0, g.ei, g.ej, g.Rm.reshape(-1, 9), g.tm,
                               g.kappa, g.tau, pgo_default_options(**opt)))
 
     @classmethod
-    def from_batch(cls, batch, **opt):
+    def from_batch(cls, batch, info=None, **opt):
         voff, eoff = batch.offsets()
         c = batch.concat()
+        if info is not None:
+            return cls(pgo_create_info(voff, eoff, c["R0"].reshape(-1, 9), c["t0"], c["ei"], c["ej"],
+                                       c["Rm"].reshape(-1, 9), c["tm"], c["kappa"], info,
+                                       pgo_default_options(**opt)))
         return cls(pgo_create_batched(voff, eoff, c["R0"].reshape(-1, 9), c["t0"], c["ei"], c["ej"],
                                       c["Rm"].reshape(-1, 9), c["tm"], c["kappa"], c["tau"],
                                       pgo_default_options(**opt)))

@@ -47,6 +47,10 @@ struct pgo_graph {
   hipStream_t stream = nullptr;
   pgo_options opt{};
   bool chordal = false;             // PGO_MODEL_CHORDAL
+  bool aniso = false;               // PGO_MODEL_QUAT_INFO
+  double* S9 = nullptr;             // information model: S_e per edge, caller order (m x 9)
+  void *o_Sa = nullptr, *o_Sb = nullptr, *i_Sa = nullptr, *i_Sb = nullptr;
+  void *cTa = nullptr, *cTb = nullptr, *cSa = nullptr, *cSb = nullptr;
   int64_t n = 0, m = 0;
   int32_t G = 0;
   int32_t max_n = 0;
@@ -203,7 +207,16 @@ DevChordal<T> viewc(const pgo_graph* g) {
 // z in LDS (the rule of launch_graph_sweeps: (4 + 4) words x max_n <= 160 KiB).
 bool lds_fits(const pgo_graph* g) {
   const size_t w = g->opt.precision == PGO_FP64 ? 8 : 4;
-  return !g->chordal && 8 * w * size_t(g->max_n) <= 160 * 1024;
+  return !g->chordal && !g->aniso && 8 * w * size_t(g->max_n) <= 160 * 1024;
+}
+
+template <typename T>
+DevAniso<T> viewa(const pgo_graph* g) {
+  return DevAniso<T>{view<T>(g),
+                     static_cast<const P4<T>*>(g->o_Sa), static_cast<const P4<T>*>(g->o_Sb),
+                     static_cast<const P4<T>*>(g->i_Sa), static_cast<const P4<T>*>(g->i_Sb),
+                     static_cast<const P4<T>*>(g->cTa), static_cast<const P4<T>*>(g->cTb),
+                     static_cast<const P4<T>*>(g->cSa), static_cast<const P4<T>*>(g->cSb)};
 }
 
 // words of T per vertex of a rotation-like block (p, q, lambda and edge w)
@@ -227,8 +240,10 @@ pgo_status check_options(const pgo_options& o) {
     return fail(PGO_EINVAL, "unknown schedule");
   if (o.block != 0 && (o.block < 64 || o.block > 1024 || o.block % 64 != 0))
     return fail(PGO_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
-  if (o.model != PGO_MODEL_QUAT && o.model != PGO_MODEL_CHORDAL)
-    return fail(PGO_EINVAL, "model must be PGO_MODEL_QUAT or PGO_MODEL_CHORDAL");
+  if (o.model != PGO_MODEL_QUAT && o.model != PGO_MODEL_CHORDAL && o.model != PGO_MODEL_QUAT_INFO)
+    return fail(PGO_EINVAL, "model must be PGO_MODEL_QUAT, PGO_MODEL_CHORDAL or PGO_MODEL_QUAT_INFO");
+  if (o.model == PGO_MODEL_QUAT_INFO && o.block > 256)
+    return fail(PGO_EINVAL, "the information model runs at most 256 threads per workgroup");
   return PGO_OK;
 }
 
@@ -317,6 +332,14 @@ pgo_status alloc_precision(pgo_graph* g) {
   void** c1[] = {&g->cQ, &g->cT, &g->cS};
   for (void** v : c1)
     if ((s = dalloc_bytes(g, v, sizeof(T) * n)) != PGO_OK) return s;
+  if (g->aniso) {
+    void** es[] = {&g->o_Sa, &g->o_Sb, &g->i_Sa, &g->i_Sb};
+    for (void** v : es)
+      if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * m)) != PGO_OK) return s;
+    void** vs[] = {&g->cTa, &g->cTb, &g->cSa, &g->cSb};
+    for (void** v : vs)
+      if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * n)) != PGO_OK) return s;
+  }
   return PGO_OK;
 }
 
@@ -341,6 +364,15 @@ pgo_status prepare_precision(pgo_graph* g, const double* t0_dev) {
   HIPCHK(launch_vertex_consts<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->tm,
                                  g->kappa, g->tau, static_cast<T*>(g->cQ),
                                  static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
+  if (g->aniso) {
+    HIPCHK(launch_fill_edges_a<T>(g->o_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->o_tt),
+                                  static_cast<P4<T>*>(g->o_Sa), static_cast<P4<T>*>(g->o_Sb), st));
+    HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
+                                  static_cast<P4<T>*>(g->i_Sa), static_cast<P4<T>*>(g->i_Sb), st));
+    HIPCHK(launch_vertex_consts_a<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->S9,
+                                     static_cast<P4<T>*>(g->cTa), static_cast<P4<T>*>(g->cTb),
+                                     static_cast<P4<T>*>(g->cSa), static_cast<P4<T>*>(g->cSb), st));
+  }
   HIPCHK(launch_init_state<T>(view<T>(g), g->p0, t0_dev, st));
   return PGO_OK;
 }
@@ -394,19 +426,22 @@ void choose_default_schedule(pgo_graph* g) {
     g->block_graph = g->opt.block;
   } else {
     g->block_phase = 256;
-    g->block_graph = g->max_n >= 2048 ? 512 : 256;
+    g->block_graph = (g->max_n >= 2048 && !g->aniso) ? 512 : 256;
   }
 }
 
 pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const int64_t* eoff,
                        const double* R0, const double* t0, const int32_t* ei, const int32_t* ej,
                        const double* Rm, const double* tm, const double* kappa, const double* tau,
-                       const pgo_options* opt_in) {
+                       const pgo_options* opt_in, const double* info = nullptr) {
   if (!out) return fail(PGO_EINVAL, "out must not be NULL");
   *out = nullptr;
   pgo_options opt;
   pgo_default_options(&opt);
   if (opt_in) opt = *opt_in;
+  if (info) opt.model = PGO_MODEL_QUAT_INFO;
+  else if (opt.model == PGO_MODEL_QUAT_INFO)
+    return fail(PGO_EINVAL, "PGO_MODEL_QUAT_INFO handles are made by pgo_create_info");
   pgo_status s = check_options(opt);
   if (s != PGO_OK) return s;
   if (!voff || !eoff) return fail(PGO_EINVAL, "voff and eoff must not be NULL");
@@ -423,6 +458,7 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   g->device = opt.device;
   g->opt = opt;
   g->chordal = opt.model == PGO_MODEL_CHORDAL;
+  g->aniso = opt.model == PGO_MODEL_QUAT_INFO;
   g->G = G;
   g->n = voff[G];
   g->m = eoff[G];
@@ -474,6 +510,7 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
   if ((s = upload(g, &g->tm, tm, size_t(3 * m))) != PGO_OK) return bail(s);
   if ((s = upload(g, &g->kappa, kappa, size_t(m))) != PGO_OK) return bail(s);
   if ((s = upload(g, &g->tau, tau, size_t(m))) != PGO_OK) return bail(s);
+  if (info && (s = upload(g, &g->S9, info, size_t(9 * m))) != PGO_OK) return bail(s);
   if ((s = upload(g, &R0d, R0, size_t(9 * n))) != PGO_OK) return bail(s);
   if ((s = upload(g, &t0d, t0, size_t(3 * n))) != PGO_OK) return bail(s);
   if ((s = upload(g, &Rmd, Rm, size_t(9 * m))) != PGO_OK) return bail(s);
@@ -578,9 +615,12 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
                  per_graph ? g->beta_dev : nullptr, masked ? g->active_dev : nullptr};
   const DevGraph<T> d = view<T>(g);
   const DevChordal<T> dc = viewc<T>(g);
+  const DevAniso<T> da = viewa<T>(g);
   if (sched == PGO_SCHED_GRAPH) {
     if (g->chordal)
       HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->stream));
+    else if (g->aniso)
+      HIPCHK(launch_graph_sweeps_a<T>(da, g->voff32, g->order, g->G, k, sp, block, g->stream));
     else
       HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->max_n,
                                     g->graph_lds, g->stream));
@@ -588,6 +628,7 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
   }
   auto phases = [&](hipStream_t st) {
     return g->chordal ? launch_phase_sweeps_c<T>(dc, k, sp, block, st)
+           : g->aniso ? launch_phase_sweeps_a<T>(da, k, sp, block, st)
                       : launch_phase_sweeps<T>(d, k, sp, block, st);
   };
   // per-phase launches, captured once into a HIP graph per (k, beta, gamma, block)
@@ -656,7 +697,7 @@ pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int 
 // non-finite value anywhere is reported as PGO_ENUMERIC.
 pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite = false) {
   HIPCHK(hipSetDevice(g->device));
-  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9};
+  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9, g->S9};
   hipError_t he;
   if (g->chordal && g->opt.precision == PGO_FP64)
     he = launch_reduce_c<double>(viewc<double>(g), e, g->have_prev, g->ec_beg, g->ec_end, g->n_ech,
@@ -842,6 +883,15 @@ pgo_status refill_edges(pgo_graph* g) {
   HIPCHK(launch_vertex_consts<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->tm,
                                  g->kappa, g->tau, static_cast<T*>(g->cQ),
                                  static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
+  if (g->aniso) {  // edge records (t~, c) and the information sums
+    HIPCHK(launch_fill_edges_a<T>(g->o_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->o_tt),
+                                  static_cast<P4<T>*>(g->o_Sa), static_cast<P4<T>*>(g->o_Sb), st));
+    HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
+                                  static_cast<P4<T>*>(g->i_Sa), static_cast<P4<T>*>(g->i_Sb), st));
+    HIPCHK(launch_vertex_consts_a<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->S9,
+                                     static_cast<P4<T>*>(g->cTa), static_cast<P4<T>*>(g->cTb),
+                                     static_cast<P4<T>*>(g->cSa), static_cast<P4<T>*>(g->cSb), st));
+  }
   return PGO_OK;
 }
 
@@ -915,8 +965,8 @@ hipError_t state_io(pgo_graph* g, double* buf, int to_device) {
 }
 
 pgo_status quaternion_only(pgo_graph* g, const char* what) {
-  if (!g->chordal) return PGO_OK;
-  return fail(PGO_ESTATE, std::string(what) + " exists for the quaternion model only");
+  if (!g->chordal && !g->aniso) return PGO_OK;
+  return fail(PGO_ESTATE, std::string(what) + " exists for the isotropic quaternion model only");
 }
 
 }  // namespace
@@ -953,6 +1003,43 @@ pgo_status pgo_create_batched(pgo_graph** out, int32_t G, const int64_t* voff,
                               const double* tm, const double* kappa, const double* tau,
                               const pgo_options* opt) {
   return create_impl(out, G, voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, tau, opt);
+}
+
+pgo_status pgo_create_info(pgo_graph** out, int32_t G, const int64_t* voff, const int64_t* eoff,
+                           const double* R0, const double* t0, const int32_t* ei,
+                           const int32_t* ej, const double* Rm, const double* tm,
+                           const double* kappa, const double* info, const pgo_options* opt) {
+  if (!out) return fail(PGO_EINVAL, "out must not be NULL");
+  *out = nullptr;
+  if (G < 1 || !voff || !eoff) return fail(PGO_EINVAL, "need G >= 1 and offsets");
+  const int64_t m = eoff[G];
+  if (m > 0 && !info) return fail(PGO_EINVAL, "info must not be NULL");
+  // each S_e: finite, symmetric, positive definite; c_e = trace / 3 stands in for tau
+  std::vector<double> c(static_cast<size_t>(std::max<int64_t>(m, 0)));
+  for (int64_t e = 0; e < m; ++e) {
+    const double* S = info + 9 * e;
+    double big = 0.0;
+    for (int k = 0; k < 9; ++k) {
+      if (!std::isfinite(S[k]))
+        return fail(PGO_EINVAL, "info of edge " + std::to_string(e) + " is not finite");
+      big = std::max(big, std::fabs(S[k]));
+    }
+    if (std::fabs(S[1] - S[3]) > 1e-12 * big || std::fabs(S[2] - S[6]) > 1e-12 * big ||
+        std::fabs(S[5] - S[7]) > 1e-12 * big)
+      return fail(PGO_EINVAL, "info of edge " + std::to_string(e) + " is not symmetric");
+    const double l11 = S[0] > 0 ? std::sqrt(S[0]) : 0.0;
+    const double l21 = l11 > 0 ? S[3] / l11 : 0.0, l31 = l11 > 0 ? S[6] / l11 : 0.0;
+    const double d2 = S[4] - l21 * l21;
+    const double l22 = d2 > 0 ? std::sqrt(d2) : 0.0;
+    const double l32 = l22 > 0 ? (S[7] - l31 * l21) / l22 : 0.0;
+    const double d3 = S[8] - l31 * l31 - l32 * l32;
+    if (!(l11 > 0 && d2 > 0 && d3 > 0))
+      return fail(PGO_EINVAL, "info of edge " + std::to_string(e) + " is not positive definite");
+    c[size_t(e)] = (S[0] + S[4] + S[8]) / 3.0;
+  }
+  static const double no_edges[9] = {};
+  return create_impl(out, G, voff, eoff, R0, t0, ei, ej, Rm, tm, kappa, c.data(), opt,
+                     info ? info : no_edges);
 }
 
 pgo_status pgo_set_stream(pgo_graph* g, void* hip_stream) {
@@ -1202,9 +1289,12 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
     int sched, block, lds;
   };
   std::vector<Cand> cands;
-  for (int b : {64, 128, 256, 512}) cands.push_back({PGO_SCHED_PHASE, b, 0});
+  const int bmax = g->aniso ? 256 : 1024;
+  for (int b : {64, 128, 256, 512})
+    if (b <= bmax) cands.push_back({PGO_SCHED_PHASE, b, 0});
   if (g->max_n <= PGO_GRAPH_SCHED_MAX_N)
     for (int b : {128, 256, 512, 1024}) {
+      if (b > bmax) continue;
       cands.push_back({PGO_SCHED_GRAPH, b, 0});
       if (lds_fits(g)) cands.push_back({PGO_SCHED_GRAPH, b, 1});
     }

@@ -134,6 +134,37 @@ hipError_t launch_state_io(const DevGraph<T>& g, double* buf, int to_device, hip
 template <typename T>
 hipError_t launch_poses(const DevGraph<T>& g, double* R, double* t, hipStream_t st);
 
+// Quaternion model with a full 3x3 translation information per edge
+// (aniso.hip): the isotropic view plus the edge information matrices (two
+// P4 per edge: xx xy xz yy | yz zz) in both orders, the edge record tt
+// holding (t~, c_e) instead of (tau t~, tau), and the vertex sums
+// 2 sum_in S (cT) and 2 sum_out S (cS).
+template <typename T>
+struct DevAniso {
+  DevGraph<T> g;
+  const P4<T>* o_Sa;
+  const P4<T>* o_Sb;
+  const P4<T>* i_Sa;
+  const P4<T>* i_Sb;
+  const P4<T>* cTa;
+  const P4<T>* cTb;
+  const P4<T>* cSa;
+  const P4<T>* cSb;
+};
+template <typename T>
+hipError_t launch_phase_sweeps_a(const DevAniso<T>& a, int k, const SweepParams& sp, int block,
+                                 hipStream_t st);
+template <typename T>
+hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, const int32_t* order,
+                                 int G, int k, const SweepParams& sp, int block, hipStream_t st);
+template <typename T>
+hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const double* S9, int64_t m,
+                               P4<T>* tt, P4<T>* Sa, P4<T>* Sb, hipStream_t st);
+template <typename T>
+hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
+                                  const int32_t* i_ptr, const int32_t* i_perm, const double* S9,
+                                  P4<T>* cTa, P4<T>* cTb, P4<T>* cSa, P4<T>* cSb, hipStream_t st);
+
 // Chordal model (chordal.hip): sweeps, preparation and state transfer.
 template <typename T>
 hipError_t launch_phase_sweeps_c(const DevChordal<T>& g, int k, const SweepParams& sp, int block,
@@ -233,6 +264,7 @@ struct EdgeF64 {  // caller-order FP64 copy of the prepared edges for the cost
   const double* kappa;
   const double* tau;
   const double* R9;  // chordal model: projected measured rotations (m x 9), else unused
+  const double* S9;  // information model: translation information per edge (m x 9), else null
 };
 // Per-graph reduction output, kRedVals doubles per graph:
 enum RedIdx {

@@ -24,7 +24,18 @@ __device__ void block_sum(double (&v)[K], double (*sh)[kRB]) {
   for (int k = 0; k < K; ++k) v[k] = sh[k][0];
 }
 
-// cost term of edge e (model (1), Sigma1 = tau I_4, Sigma2 = kappa I_4)
+// |r|^2_{Sigma1} of a translation residual r = (r0, r1, r2, r3): tau |r|^2,
+// or with a full information matrix c r0^2 + r_v^T S r_v (c = trace(S) / 3)
+__device__ __forceinline__ double weighted_r(const EdgeF64& E, int64_t e, double r0, double r1,
+                                             double r2, double r3) {
+  if (!E.S9) return E.tau[e] * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3);
+  const double* S = E.S9 + 9 * e;
+  const double c = (S[0] + S[4] + S[8]) / 3.0;
+  return c * r0 * r0 + r1 * (S[0] * r1 + S[1] * r2 + S[2] * r3) +
+         r2 * (S[3] * r1 + S[4] * r2 + S[5] * r3) + r3 * (S[6] * r1 + S[7] * r2 + S[8] * r3);
+}
+
+// cost term of edge e (model (1), Sigma1 = tau I_4 or diag(c, S), Sigma2 = kappa I_4)
 template <typename T>
 __device__ double edge_cost(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
   const int i = E.ei[e], j = E.ej[e];
@@ -38,7 +49,7 @@ __device__ double edge_cost(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
   const double r3 = (double(tj.z) - double(ti.z)) - rot.z;
   const Q4<double> a = qmul(qmul(qconj(pj), pi), E.q[e]);  // p_j^* p_i q~
   const double a0 = a.w - 1.0;
-  return E.tau[e] * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3) +
+  return weighted_r(E, e, r0, r1, r2, r3) +
          E.kappa[e] * (a0 * a0 + a.x * a.x + a.y * a.y + a.z * a.z);
 }
 
@@ -57,7 +68,7 @@ __device__ double edge_split(const DevGraph<T>& g, const EdgeF64& E, int64_t e) 
   const double r3 = (double(tj.z) - double(si.z)) - rot.z;
   const Q4<double> a = qmul(qmul(qconj(pj), qi), E.q[e]);
   const double a0 = a.w - 1.0;
-  return E.tau[e] * (r0 * r0 + r1 * r1 + r2 * r2 + r3 * r3) +
+  return weighted_r(E, e, r0, r1, r2, r3) +
          E.kappa[e] * (a0 * a0 + a.x * a.x + a.y * a.y + a.z * a.z);
 }
 

@@ -96,3 +96,27 @@ def test_null_handle_calls(pgo):
         with pytest.raises(pgo.PgoError):
             fn()
     pgo.pgo_destroy(None)
+
+
+@pytest.mark.parametrize("mutate,match", [
+    (lambda S: S.__setitem__((0, 1), S[0, 1] + 1.0), "not symmetric"),
+    (lambda S: S.__setitem__((1, slice(None)), -S[1]), "not positive definite"),
+    (lambda S: S.__setitem__((0, 4), np.nan), "not finite"),
+])
+def test_create_info_rejects_bad_information(pgo, mutate, match):
+    a = _tiny()
+    S = np.tile(np.eye(3).reshape(1, 9), (2, 1))
+    mutate(S)
+    _expect_einval(pgo, lambda: pgo.pgo_create_info([0, 3], [0, 2], a["R0"], a["t0"], a["ei"], a["ej"],
+                                                    a["Rm"], a["tm"], a["kappa"], S), match)
+
+
+def test_information_model_needs_its_own_constructor(pgo):
+    a = _tiny()
+    o = pgo.pgo_default_options(model="info")
+    _expect_einval(pgo, lambda: pgo.pgo_create(a["n"], a["R0"], a["t0"], a["ei"], a["ej"], a["Rm"],
+                                               a["tm"], a["kappa"], a["tau"], o), "pgo_create_info")
+    o = pgo.pgo_default_options(block=512)
+    S = np.tile(np.eye(3).reshape(1, 9), (2, 1))
+    _expect_einval(pgo, lambda: pgo.pgo_create_info([0, 3], [0, 2], a["R0"], a["t0"], a["ei"], a["ej"],
+                                                    a["Rm"], a["tm"], a["kappa"], S, o), "256")

@@ -1,0 +1,145 @@
+"""GPU parity of the information model (pgo_create_info: a full 3x3
+translation information matrix per edge, Lemma 1's sphere-constrained p
+update) against the FP64 CPU oracle of oracle/aniso.py on the same seeded
+inputs.  Tolerances as the isotropic tests: FP64 1e-10, FP32 1e-4 max-abs
+after 10 sweeps, multipliers as lambda/beta, z/beta, every block divided by
+L = max(1, max|t| / 10 m)."""
+import numpy as np
+import pytest
+import torch
+
+import pgo_synth as S
+from oracle import aniso as A
+from oracle import pradmm as O
+
+pytestmark = pytest.mark.gpu
+
+GAMMA = 1.4
+
+
+def abar(g):
+    d = np.zeros(g.n)
+    np.add.at(d, g.ei, 2 * (g.tau * (g.tm ** 2).sum(1) + g.kappa))
+    np.add.at(d, g.ej, 2 * g.kappa)
+    return float(d.mean())
+
+
+def pack(st):
+    return np.concatenate([st[k].numpy() for k in ("p", "q", "t", "s", "lam", "z")], 1)
+
+
+def scaled_err(a, b, beta):
+    sl = dict(p=slice(0, 4), q=slice(4, 8), t=slice(8, 11), s=slice(11, 14), lam=slice(14, 18),
+              z=slice(18, 21))
+    L = max(1.0, float(np.abs(b[:, 8:11]).max()) / 10.0)
+    return {k: float(np.abs(a[:, s] - b[:, s]).max()) / (beta if k in ("lam", "z") else 1.0) / L
+            for k, s in sl.items()}
+
+
+def assert_parity(errs, tol, label=""):
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, f"{label} exceeds {tol}: {bad}"
+
+
+def oracle_run(g, info, k, beta):
+    P, p0, t0 = A.prepare(g.n, g.ei, g.ej, g.Rm, g.tm, g.kappa, info, g.R0, g.t0)
+    st, prev = A.iterate(P, O.init_state(p0, t0), k, beta, GAMMA, return_prev=True)
+    return P, st, prev
+
+
+def gpu_run(pgo, g, info, k, beta, **opt):
+    with pgo.PoseGraph.from_graph(g, info=info, **opt) as h:
+        h.iterate(k, beta, GAMMA)
+        return h.state(), h.cost()[0], h.residuals()[0]
+
+
+CASES = [("circle-100", 30.0), ("grid-1k", 10.0)]
+
+
+@pytest.mark.parametrize("name,aniso", CASES)
+@pytest.mark.parametrize("sched", ["phase", "graph"])
+def test_fp64_parity_10_sweeps(pgo, name, aniso, sched):
+    g = S.make_config(name)
+    info = S.random_info(g.m, g.tau, aniso, seed=1)
+    beta = 0.01 * abar(g)
+    _, st, _ = oracle_run(g, info, 10, beta)
+    got, _, _ = gpu_run(pgo, g, info, 10, beta, precision="fp64", schedule=sched)
+    assert_parity(scaled_err(got, pack(st), beta), 1e-10, f"{name}/{sched}")
+
+
+@pytest.mark.parametrize("name,aniso", CASES)
+def test_fp32_parity_10_sweeps(pgo, name, aniso):
+    g = S.make_config(name)
+    info = S.random_info(g.m, g.tau, aniso, seed=1)
+    beta = 0.01 * abar(g)
+    _, st, _ = oracle_run(g, info, 10, beta)
+    for sched in ("phase", "graph"):
+        got, _, _ = gpu_run(pgo, g, info, 10, beta, precision="fp32", schedule=sched)
+        assert_parity(scaled_err(got, pack(st), beta), 1e-4, f"{name}/fp32/{sched}")
+
+
+def test_isotropic_information_equals_the_isotropic_model(pgo):
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    info = g.tau[:, None, None] * np.eye(3)
+    a, Fa, ra = gpu_run(pgo, g, info, 10, beta, precision="fp64")
+    b, Fb, rb = gpu_run(pgo, g, None, 10, beta, precision="fp64")
+    assert_parity(scaled_err(a, b, beta), 1e-10, "isotropic")
+    assert abs(Fa - Fb) <= 1e-11 * Fb
+
+
+def test_schedules_and_blocks_bitwise(pgo):
+    g = S.make_config("sphere-2.5k")
+    info = S.random_info(g.m, g.tau, 10.0, seed=2)
+    beta = 0.01 * abar(g)
+    for prec in ("fp64", "fp32"):
+        ref = None
+        for sched in ("phase", "graph"):
+            for block in (64, 256):
+                got, _, _ = gpu_run(pgo, g, info, 6, beta, precision=prec, schedule=sched, block=block)
+                if ref is None:
+                    ref = got
+                assert np.array_equal(got, ref), (prec, sched, block)
+        assert np.abs(np.linalg.norm(ref[:, 0:4], axis=1) - 1).max() < (1e-14 if prec == "fp64" else 1e-6)
+
+
+def test_cost_residuals_merit_and_batch(pgo):
+    g = S.make_config("grid-1k")
+    info = S.random_info(g.m, g.tau, 10.0, seed=3)
+    beta = 0.01 * abar(g)
+    P, st, prev = oracle_run(g, info, 7, beta)
+    a1 = abs(1 - GAMMA) / (1 - abs(1 - GAMMA))
+    L_ref = float(A.aug_lagrangian(P, st, beta))
+    psi_ref = L_ref + a1 / (GAMMA * beta) * float(((st["lam"] - prev["lam"]) ** 2).sum())
+    F_ref = float(A.cost(P, st["p"], st["t"]))
+    res_ref = O.residuals(P, prev, st, beta)
+    with pgo.PoseGraph.from_graph(g, info=info, precision="fp64") as h:
+        h.iterate(7, beta, GAMMA)
+        F, res, mer = h.cost()[0], h.residuals()[0], h.merit()[0]
+    assert abs(F - F_ref) <= 1e-11 * F_ref
+    assert np.allclose(res[:5], res_ref[:5], rtol=1e-9, atol=1e-12)
+    assert abs(mer[0] - L_ref) <= 1e-10 * abs(L_ref) and abs(mer[1] - psi_ref) <= 1e-10 * abs(psi_ref)
+    # a batch equals its graphs one by one, bit for bit
+    b = S.batched(4096, first=300, count=5)
+    infos = [S.random_info(gr.m, gr.tau, 10.0, seed=k) for k, gr in enumerate(b.graphs)]
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs])
+    voff, _ = b.offsets()
+    with pgo.PoseGraph.from_batch(b, info=np.concatenate(infos), precision="fp32") as h:
+        h.iterate(6, betas, GAMMA)
+        allst = h.state()
+    for k, gr in enumerate(b.graphs):
+        got, _, _ = gpu_run(pgo, gr, infos[k], 6, betas[k], precision="fp32")
+        assert np.array_equal(allst[voff[k]:voff[k + 1]], got), k
+
+
+def test_solve_and_unsupported_calls(pgo):
+    g = S.make_config("circle-100")
+    info = S.random_info(g.m, g.tau, 10.0, seed=4)
+    with pgo.PoseGraph.from_graph(g, info=info) as h:
+        F0 = h.cost()[0]
+        _, done, _ = h.solve(200, 50, GAMMA, np.array([0.01 * abar(g)]))
+        assert done[0] == 200 and h.cost()[0] < F0
+        assert h.info()["model"] == pgo.MODEL_QUAT_INFO
+        with pytest.raises(pgo.PgoError) as ex:
+            pgo.pgo_forward_record(h.h, 3, 1.0, GAMMA, 1)
+        assert ex.value.name == "PGO_ESTATE"
