@@ -46,6 +46,8 @@ B_EDGE_PHASE, B_VERTEX_PHASE = 116, 448
 # the rotation-matrix rendering: edge (kappa, tau 8, t~ 12, R~ 36, two indices
 # 8) = 64 B; pose state P, Q, Lambda, t, s, z = 36 words read and written
 B_EDGE_CHORDAL, B_VERTEX_CHORDAL = 64, 288
+# the information model: the isotropic edge plus the 6 unique entries of S_e
+B_EDGE_INFO = B_EDGE + 24
 GAMMA = 1.4
 BETA_SCALE = 0.01
 
@@ -102,7 +104,7 @@ def copy_calibration(torch, gib=1):
 
 
 def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tune, sched, block,
-              edges_per_graph, model="quat"):
+              edges_per_graph, model="quat", info=None):
     """One handle over the whole batch.  A step is one chunk of the
     merit-checked solve: one persistent launch of `sweeps` sweeps for every
     graph still running, the FP64 cost/residual/merit reductions of every
@@ -113,10 +115,15 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
     persistent launch alone is also timed with hipEvents on the handle's
     stream for the roofline (3 launches of `sweeps` sweeps, every graph)."""
     stream = torch.cuda.Stream()
-    opt = P.pgo_default_options(precision=prec, schedule=sched, block=block, model=model)
+    opt = P.pgo_default_options(precision=prec, schedule=sched, block=block,
+                                model=model if info is None else "quat")
     t0 = time.perf_counter()
-    h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
-                             cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], cat["tau"], opt)
+    if info is None:
+        h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
+                                 cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], cat["tau"], opt)
+    else:
+        h = P.pgo_create_info(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
+                              cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], info, opt)
     create_s = time.perf_counter() - t0
     P.pgo_set_stream(h, stream.cuda_stream)
     info = P.pgo_autotune(h, float(np.median(betas)), GAMMA, sweeps=10) if tune else P.pgo_info(h)
@@ -277,6 +284,7 @@ def main():
     ap.add_argument("--skip-fp64", action="store_true")
     ap.add_argument("--skip-chordal", action="store_true", help="skip the rotation-matrix model leg")
     ap.add_argument("--skip-cinit", action="store_true", help="skip the chordal-initialisation leg")
+    ap.add_argument("--skip-info", action="store_true", help="skip the information-model leg")
     ap.add_argument("--skip-ttt", action="store_true", help="skip the time-to-tolerance leg")
     ap.add_argument("--no-tune", action="store_true", help="use --schedule/--block as given")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phase", "graph"])
@@ -375,6 +383,27 @@ def main():
                          "bytes_model": f"{B_EDGE_CHORDAL} B/edge + {B_VERTEX_CHORDAL} B/pose per "
                                         f"sweep x {args.sweeps} sweeps"},
             "batch_health": health(rc, betas)}
+    if not args.skip_info:
+        # the information model on the same batch: S_e = tau_e R diag(a) R^T
+        # with eigenvalue ratios up to 10 (FP32)
+        info = S.random_info(m, cat["tau"], 10.0, seed=0)
+        sti = max(2, args.steps // 2) if args.steps else 0
+        ri = run_batch(P, torch, cat, voff, eoff, "fp32", betas, args.sweeps, sti,
+                       max(1, args.warmup // 2) if args.steps else 0, tune,
+                       "auto" if args.schedule == "auto" else args.schedule,
+                       min(args.block, 256), epg, info=info)
+        del info
+        ib = (B_EDGE_INFO * m + B_VERTEX * n) * args.sweeps
+        ia = ib / (ri["kern_ms"] * 1e-3) / 1e9
+        out["information_model"] = {
+            "value": ri["edge_iters"] / ri["wall"] if sti else None, "unit": "edge-iter/s",
+            "steps": sti, "dtype": "f32",
+            "kernel": ("k_graph_sweeps_a<float>" if ri["info"]["schedule"] == 2 else "k_phase_a<*,float>"),
+            "kernel_ms_per_launch": ri["kern_ms"],
+            "roofline": {"bound": "hbm", "achieved": ia, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ia / HBM_PEAK_GBS,
+                         "bytes_model": f"{B_EDGE_INFO} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps"},
+            "batch_health": health(ri, betas)}
     if not args.skip_cinit:
         out["chordal_init"] = cinit_leg(P, torch, cat, voff, eoff, args.steps)
     if not args.skip_ttt:
