@@ -279,8 +279,9 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
  * Jacobi-preconditioned conjugate gradients per graph, from the current
  * initial point, until <r, M^-1 r> <= tol^2 of its starting value or
  * max_iters iterations.  The result replaces the handle's initial point
- * (quaternion model: p^0 and the sign alignment of every edge, R7) and the
- * state is reset to it (as pgo_reset_state).
+ * (quaternion model: p^0, and each edge quaternion's sign aligned against
+ * the new p^0 as at create) and the state is reset to it (as
+ * pgo_reset_state).
  *   max_iters >= 1; tol in (0, 1)
  *   iters  out, G x 2 (iterations of the rotation and translation solves),
  *          may be NULL

@@ -13,8 +13,8 @@ g = W^T b1, lambda* > -a_min solves h(lambda) = sum g_k^2 / (a_k + lambda)^2
 - 1 = 0 (a library bracketing root finder on that equation), p =
 -(A1 + lambda* I)^{-1} b1; in the hard case (g vanishing on the lowest
 eigenspace and h(-a_min) <= 0) lambda* = -a_min and p is the pseudo-inverse
-solution plus the null-space component that brings the norm to 1 (sign:
-the one closer to p^k).  That lambda* is the rightmost real eigenvalue of
+solution plus the lowest-eigenspace component that brings the norm to 1,
+the one of those minimisers nearest p^k.  That lambda* is the rightmost real eigenvalue of
 Alg. 2's 8x8 matrix is a pin (tests), not the method used here, because a
 nonsymmetric eigensolver loses accuracy near the hard case.
 
@@ -80,9 +80,13 @@ def trs_sphere(A, b, p_prev):
     lam = -float(w[0])
     x0 = -(V[:, ~low] @ (g[~low] / (w[~low] + lam)))
     rem = max(0.0, 1.0 - float(x0 @ x0))
-    v = V[:, 0]
-    sgn = 1.0 if float(v @ p_prev) >= 0.0 else -1.0
-    return x0 + sgn * np.sqrt(rem) * v, lam
+    # the minimisers are x0 + y, y in the lowest eigenspace with |y|^2 = rem;
+    # take the one nearest p_prev: y along p_prev's projection on that space
+    Vl = V[:, low]
+    u = Vl @ (Vl.T @ np.asarray(p_prev, np.float64))
+    nu = float(np.linalg.norm(u))
+    u = u / nu if nu > 0.0 else Vl[:, 0]
+    return x0 + np.sqrt(rem) * u, lam
 
 
 def alg2_multiplier(A, b):

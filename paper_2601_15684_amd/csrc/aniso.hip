@@ -9,8 +9,8 @@
 //      p_i = argmin_{|p| = 1} 1/2 p^T A1 p + b1^T p   (Lemma 1; solved in FP64
 //      from A1 = W diag(a) W^T by the secular equation of Lemma B.1 (ii):
 //      Newton on 1/|x(lambda)| - 1 with bisection safeguards, x(lambda) =
-//      -(A1 + lambda I)^{-1} b1, lambda > -a_min; the hard case keeps the
-//      null-space component on the side of p_i^k);
+//      -(A1 + lambda I)^{-1} b1, lambda > -a_min; in the hard case, of the
+//      minimisers the one nearest p_i^k);
 //   Q  A2 = 2 sum_out (G3^T Sigma1 G3 + kappa |p_j|^2 I) + (beta + H2) I,
 //      b2 = 2 sum_out (G3^T Sigma1 [0, t_j - s_i] + p_j (x) (kappa q~)^*)
 //           + beta p_i - lambda_i + H2 q_i,  q_i = A2^{-1} b2  (App. B.2);
@@ -197,10 +197,17 @@ __device__ void trs4(const double M[10], const double b[4], const double pprev[4
       for (int r = 0; r < 4; ++r) x[r] += V[r][k] * ck;
     }
   const double rem = sqrt(fmax(0.0, 1.0 - n0));
-  const double side = V[0][kmin] * pprev[0] + V[1][kmin] * pprev[1] + V[2][kmin] * pprev[2] +
-                      V[3][kmin] * pprev[3];
-  const double sgn = side >= 0.0 ? 1.0 : -1.0;
-  for (int r = 0; r < 4; ++r) x[r] += sgn * rem * V[r][kmin];
+  // the minimisers are x + y, y in the lowest eigenspace with |y| = rem;
+  // the one nearest p^k takes y along p^k's projection on that space
+  double y[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < 4; ++k)
+    if (low[k]) {
+      const double d = V[0][k] * pprev[0] + V[1][k] * pprev[1] + V[2][k] * pprev[2] +
+                       V[3][k] * pprev[3];
+      for (int r = 0; r < 4; ++r) y[r] += d * V[r][k];
+    }
+  const double ny = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2] + y[3] * y[3]);
+  for (int r = 0; r < 4; ++r) x[r] += rem * (ny > 0.0 ? y[r] / ny : V[r][kmin]);
 }
 
 // SPD solves by Cholesky (upper-triangle storage)

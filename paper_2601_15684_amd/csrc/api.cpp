@@ -1507,7 +1507,7 @@ pgo_status pgo_chordal_init(pgo_graph* g, int32_t max_iters, double tol, int32_t
     uint8_t* bad = nullptr;
     if ((s = talloc(reinterpret_cast<void**>(&bad), nn)) != PGO_OK) return cleanup(s);
     HIPCHK(launch_rot_to_quat(Rp, n, g->p0, 1, bad, st));
-    HIPCHK(launch_align(g->p0, g->qe0, g->ei, g->ej, m, st));  // sign alignment (R7) anew
+    HIPCHK(launch_align(g->p0, g->qe0, g->ei, g->ej, m, st));  // edge signs aligned against the new p^0
     if (m) HIPCHK(launch_perturb(m, g->qe0, g->omega, g->qe, st));
     s = g->opt.precision == PGO_FP64 ? refill_edges<double>(g) : refill_edges<float>(g);
     if (s != PGO_OK) return cleanup(s);

@@ -91,7 +91,7 @@ def test_components_keep_their_anchors_and_noise_free_recovers_truth(pgo):
 
 
 def test_quaternion_signs_realigned(pgo):
-    """After the new p^0 every edge keeps <p_i^0 q~_e, p_j^0> >= 0 (R7)."""
+    """After the new p^0 every edge keeps <p_i^0 q~_e, p_j^0> >= 0, the sign rule of the boundary preparation."""
     from oracle.quat import qmul
     g = S.make_config("sphere-2.5k")
     with pgo.PoseGraph.from_graph(g) as h:

@@ -81,6 +81,20 @@ def test_hard_case():
     Y /= np.linalg.norm(Y, axis=1, keepdims=True)
     vals = 0.5 * np.einsum("ka,ab,kb->k", Y, Aq, Y) + Y @ bq
     assert _objective(Aq, bq, x) <= vals.min() + 1e-12
+    # every minimiser is x0 + y with y in span(V0, V1), |y|^2 = 1 - |x0|^2;
+    # the step takes the one nearest the previous iterate
+    x0 = -(V[:, 2] * 0.5 / (1.0 + 2.0) + V[:, 3] * 0.2 / (3.0 + 2.0))
+    r = np.sqrt(1.0 - x0 @ x0)
+    assert np.abs(x - (x0 + r * V[:, 0])).max() < 1e-12
+    prev = V[:, 0] - 2.0 * V[:, 1] + 0.7 * V[:, 2]
+    x2, _ = A.trs_sphere(Aq, bq, prev)
+    u = (V[:, 0] - 2.0 * V[:, 1]) / np.sqrt(5.0)
+    assert np.abs(x2 - (x0 + r * u)).max() < 1e-12
+    ang = np.random.default_rng(2).uniform(0, 2 * np.pi, 2000)
+    cand = x0[None] + r * (np.cos(ang)[:, None] * V[:, 0] + np.sin(ang)[:, None] * V[:, 1])
+    assert np.allclose(0.5 * np.einsum("ka,ab,kb->k", cand, Aq, cand) + cand @ bq,
+                       _objective(Aq, bq, x2), atol=1e-12)
+    assert np.linalg.norm(x2 - prev) <= np.linalg.norm(cand - prev, axis=1).min() + 1e-12
 
 
 def fd(f, x, h=1e-6):
