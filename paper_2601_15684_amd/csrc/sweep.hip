@@ -28,6 +28,13 @@
 // Per-vertex sums run over the CSR/CSC segment in edge order, one thread per
 // vertex, with no atomics: results are deterministic and identical between
 // the per-phase launches and the per-graph persistent kernel.
+//
+// Multiply-adds are not contracted in this file: the P update runs in two
+// code paths (alone at the start of a launch, fused with S inside it) that
+// must round identically, so k sweeps in one launch equal k sweeps over
+// several, and the compiler's choice of fused multiply-adds depends on the
+// code around an expression.
+#pragma clang fp contract(off)
 #include "internal.hpp"
 
 namespace pgo {
@@ -47,27 +54,69 @@ __device__ __forceinline__ A l1(const Q4<A>& t) {
   return fabs(t.w) + fabs(t.x) + fabs(t.y) + fabs(t.z);
 }
 
-// Sum of the edge terms of the P phase, in accumulation type A.  mag collects
+// Out-edge part of the P sum.  Each term [0, s_i - t_j] (x) q_i (x) [0, u_e]
+// (u_e = tau t~_e) is linear in s_i, so the sum over the out-edges is
+//   [0, s_i - t_i] (x) q_i (x) [0, sum u_e] + sum [0, t_i - t_j] (x) q_i (x) [0, u_e],
+// and the second sum needs no s_i: the S update of the same vertex gathers
+// it in its own pass over the out-edges, and P only finishes it once the new
+// s_i is known.  Both brackets are differences of nearby positions, which
+// keeps FP32's relative accuracy where coordinates are large.  mag collects
 // the L1 size of every term (used only by the FP32 cancellation check).
+template <typename A>
+struct POut {
+  Q4<A> x;
+  V3<A> u;
+  A mag;
+};
+
+template <typename A>
+__device__ __forceinline__ POut<A> p_out_zero() {
+  return {{A(0), A(0), A(0), A(0)}, {A(0), A(0), A(0)}, A(0)};
+}
+
+template <typename A, bool kMag, typename T>
+__device__ __forceinline__ void p_out_add(POut<A>& po, const Q4<A>& qi, const V3<A>& ti,
+                                          const P4<T>& tj_, const P4<T>& u_) {
+  const V3<A> tj = v3a<A>(tj_), u = v3a<A>(u_);
+  const V3<A> d = {ti.x - tj.x, ti.y - tj.y, ti.z - tj.z};
+  const Q4<A> term = qmul_vp(qmul_pv(d, qi), u);
+  acc4(po.x, term);
+  po.u.x += u.x;
+  po.u.y += u.y;
+  po.u.z += u.z;
+  if (kMag) po.mag += l1(term);
+}
+
+template <typename A, bool kMag>
+__device__ __forceinline__ Q4<A> p_out_finish(const POut<A>& po, const Q4<A>& qi,
+                                              const V3<A>& ti, const V3<A>& si, A& mag) {
+  const V3<A> r = {si.x - ti.x, si.y - ti.y, si.z - ti.z};
+  const Q4<A> head = qmul_vp(qmul_pv(r, qi), po.u);
+  if (kMag) mag += po.mag + l1(head);
+  return {head.w + po.x.w, head.x + po.x.x, head.y + po.x.y, head.z + po.x.z};
+}
+
+// Sum of the edge terms of the P phase, in accumulation type A; the
+// out-edge part is taken from pre when the caller gathered it already.
 template <typename A, typename T, bool kMag>
 __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, const Q4<T>& q_i,
-                                            const P4<T>& s_i, A& mag) {
+                                            const P4<T>& t_i, const P4<T>& s_i, A& mag,
+                                            const POut<A>* pre = nullptr) {
   const Q4<A> qi = cvt<A>(q_i);
-  const V3<A> si = v3a<A>(s_i);
-  Q4<A> acc = {A(0), A(0), A(0), A(0)};
-  struct OutE {
-    P4<T> tj, u;
-  };
-  edge_loop(
-      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
-      [&](const OutE& d) {
-        const V3<A> tj = v3a<A>(d.tj);
-        const V3<A> u = v3a<A>(d.u);
-        const V3<A> mr = {si.x - tj.x, si.y - tj.y, si.z - tj.z};  // [0, r]^* = [0, s_i - t_j]
-        const Q4<A> term = qmul_vp(qmul_pv(mr, qi), u);
-        acc4(acc, term);
-        if (kMag) mag += l1(term);
-      });
+  const V3<A> ti = v3a<A>(t_i);
+  POut<A> po;
+  if (pre) {
+    po = *pre;
+  } else {
+    po = p_out_zero<A>();
+    struct OutE {
+      P4<T> tj, u;
+    };
+    edge_loop(
+        g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
+        [&](const OutE& d) { p_out_add<A, kMag>(po, qi, ti, d.tj, d.u); });
+  }
+  Q4<A> acc = p_out_finish<A, kMag>(po, qi, ti, v3a<A>(s_i), mag);
   struct InE {
     Q4<T> ql, w;
   };
@@ -94,15 +143,17 @@ __device__ __forceinline__ Q4<A> p_vector(const Q4<A>& acc, const Q4<T>& q_i, co
 // multipliers lambda_i, z_i and the constants cQ_i, cT_i, cS_i.  They are
 // passed in by the caller, which keeps them in memory (per-phase launches)
 // or in registers across all sweeps of a launch (per-graph kernel).
-// P update of vertex i from its own values q_i, s_i, p_i, lambda_i (passed
-// in, so a caller that has them in registers does not reload them).
+// P update of vertex i from its own values q_i, t_i, s_i, p_i, lambda_i
+// (passed in, so a caller that has them in registers does not reload them)
+// and, from the fused S+P phase, the out-edge sum S gathered.
 template <typename T>
 __device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                             const Q4<T>& qi, const P4<T>& si, const Q4<T>& pi,
-                                             const Q4<T>& li) {
+                                             const Q4<T>& qi, const P4<T>& ti, const P4<T>& si,
+                                             const Q4<T>& pi, const Q4<T>& li,
+                                             const POut<T>* pre = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   T mag = T(0);
-  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, i, qi, si, mag);
+  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, i, qi, ti, si, mag, pre);
   const Q4<T> v = p_vector<T, T>(acc, qi, pi, li, sp);
   const T nrm = sqrt(v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z);
   if (kF32) {
@@ -110,7 +161,7 @@ __device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, int i, const 
     const T tot = T(2) * mag + T(sp.beta) * l1(qi) + l1(li) + T(sp.h1) * l1(pi);
     if (!(nrm >= T(1e-3) * tot)) {
       double dm = 0.0;
-      const Q4<double> dacc = p_edge_sum<double, T, false>(g, i, qi, si, dm);
+      const Q4<double> dacc = p_edge_sum<double, T, false>(g, i, qi, ti, si, dm);
       const Q4<double> dv = p_vector<double, T>(dacc, qi, pi, li, sp);
       const double dn = sqrt(dv.w * dv.w + dv.x * dv.x + dv.y * dv.y + dv.z * dv.z);
       if (dn > 0.0)
@@ -124,7 +175,7 @@ __device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, int i, const 
 template <typename T>
 __device__ __forceinline__ void vertex_P(const DevGraph<T>& g, int i, const SweepParams& sp,
                                          const Q4<T>& li) {
-  vertex_P_own(g, i, sp, g.q[i], g.s[i], g.p[i], li);
+  vertex_P_own(g, i, sp, g.q[i], g.t[i], g.s[i], g.p[i], li);
 }
 
 template <typename T>
@@ -198,8 +249,12 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const Swee
 template <typename T>
 __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const SweepParams& sp,
                                          bool save, V3<T>& z, T cS, Q4<T>* p_out = nullptr,
-                                         Q4<T>* q_out = nullptr, P4<T>* s_out = nullptr) {
+                                         Q4<T>* q_out = nullptr, P4<T>* t_out = nullptr,
+                                         P4<T>* s_out = nullptr, POut<T>* po = nullptr) {
+  constexpr bool kF32 = sizeof(T) == 4;
   const Q4<T> pi = g.p[i], qi = g.q[i];
+  const P4<T> ti = g.t[i], si = g.s[i];
+  const V3<T> tiv = v3(ti);
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
     P4<T> u, tj;
@@ -211,8 +266,8 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
         acc.x += d.u.u * d.tj.x - c.x;
         acc.y += d.u.u * d.tj.y - c.y;
         acc.z += d.u.u * d.tj.z - c.z;
+        if (po) p_out_add<T, kF32>(*po, qi, tiv, d.tj, d.u);  // the next P's out-edge sum
       });
-  const P4<T> ti = g.t[i], si = g.s[i];
   const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);
   const T a = cS + b + h;
@@ -229,20 +284,23 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
   if (p_out) {
     *p_out = pi;
     *q_out = qi;
+    *t_out = ti;
     *s_out = pad3(sn);
   }
 }
 
 // S of one sweep fused with P of the next: P reads no neighbour's s, only
 // its own new s and neighbour values finished before S began, so no barrier
-// is needed between them and P reuses S's own values.
+// is needed between them; P reuses S's own values and the out-edge sum S
+// gathered in its pass, so the out-edges are read once for both.
 template <typename T>
 __device__ __forceinline__ void vertex_SP(const DevGraph<T>& g, int i, const SweepParams& sp,
                                           V3<T>& z, T cS, const Q4<T>& li) {
   Q4<T> pi, qi;
-  P4<T> si;
-  vertex_S(g, i, sp, false, z, cS, &pi, &qi, &si);
-  vertex_P_own(g, i, sp, qi, si, pi, li);
+  P4<T> ti, si;
+  POut<T> po = p_out_zero<T>();
+  vertex_S(g, i, sp, false, z, cS, &pi, &qi, &ti, &si, &po);
+  vertex_P_own(g, i, sp, qi, ti, si, pi, li, &po);
 }
 
 // phase bodies with the own-only values kept in memory
