@@ -29,6 +29,12 @@
 // (gap = sigma_2 + sign(det M) sigma_3 below 1e-2 of the L1 size of all
 // terms), M_i is summed again in double from the stored float values and
 // factored in double.
+//
+// Multiply-adds are not contracted in this file: M_i is summed by two code
+// paths (alone at the start of a launch, fused with S inside it) that must
+// round identically, and the compiler's choice of fused multiply-adds
+// depends on the code around an expression.
+#pragma clang fp contract(off)
 #include <algorithm>
 
 #include "internal.hpp"
@@ -65,30 +71,70 @@ __device__ __forceinline__ A l1_9(const A m[9]) {
   return s;
 }
 
-// M_i of the P update in accumulation type A from the state in type T.
+// Out-edge part of M_i.  Each term (t_j - s_i) u_e^T (u_e = tau t~_e) is
+// linear in s_i, so the sum over the out-edges is
+//   sum (t_j - t_i) u_e^T + (t_i - s_i) (sum u_e)^T,
+// and the first sum needs no s_i: the S update of the same vertex gathers it
+// in its own pass over the out-edges, and P finishes it once the new s_i is
+// known.  Both brackets are differences of nearby positions, which keeps
+// FP32's relative accuracy where coordinates are large.
+template <typename A>
+struct MOut {
+  A acc[9], u[3], mag;
+};
+
+template <typename A>
+__device__ __forceinline__ void m_out_zero(MOut<A>& mo) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) mo.acc[k] = A(0);
+  mo.u[0] = mo.u[1] = mo.u[2] = A(0);
+  mo.mag = A(0);
+}
+
+template <typename A, bool kMag, typename T>
+__device__ __forceinline__ void m_out_add(MOut<A>& mo, const A ti[3], const P4<T>& tj,
+                                          const P4<T>& u) {
+  const A d[3] = {A(tj.x) - ti[0], A(tj.y) - ti[1], A(tj.z) - ti[2]};
+  const A uu[3] = {A(u.x), A(u.y), A(u.z)};
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mo.acc[3 * r + c] += d[r] * uu[c];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) mo.u[c] += uu[c];
+  if (kMag)
+    mo.mag += (fabs(d[0]) + fabs(d[1]) + fabs(d[2])) * (fabs(uu[0]) + fabs(uu[1]) + fabs(uu[2]));
+}
+
+// M_i of the P update in accumulation type A from the state in type T; the
+// out-edge part is taken from pre when the caller gathered it already.
 // mag collects the L1 size of every term (FP32 conditioning check only).
 template <typename A, typename T, bool kMag>
 __device__ void p_matrix(const DevChordal<T>& g, int i, const SweepParams& sp, const R3<T>& Qi_,
-                         const P4<T>& si_, const R3<T>& Pi_, const R3<T>& Li_, A M[9], A& mag) {
+                         const P4<T>& ti_, const P4<T>& si_, const R3<T>& Pi_, const R3<T>& Li_,
+                         A M[9], A& mag, const MOut<A>* pre = nullptr) {
+  const A ti[3] = {A(ti_.x), A(ti_.y), A(ti_.z)};
+  MOut<A> mo;
+  if (pre) {
+    mo = *pre;
+  } else {
+    m_out_zero(mo);
+    struct OutE {
+      P4<T> tj, u;
+    };
+    edge_loop(
+        g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
+        [&](const OutE& x) { m_out_add<A, kMag>(mo, ti, x.tj, x.u); });
+  }
+  const A ds[3] = {ti[0] - A(si_.x), ti[1] - A(si_.y), ti[2] - A(si_.z)};  // t_i - s_i
   A acc[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) acc[k] = A(0);
-  const A sx = A(si_.x), sy = A(si_.y), sz = A(si_.z);
-  struct OutE {
-    P4<T> tj, u;
-  };
-  edge_loop(
-      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
-      [&](const OutE& x) {
-        const A d[3] = {A(x.tj.x) - sx, A(x.tj.y) - sy, A(x.tj.z) - sz};
-        const A uu[3] = {A(x.u.x), A(x.u.y), A(x.u.z)};
+  for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int c = 0; c < 3; ++c) acc[3 * r + c] += d[r] * uu[c];
-        if (kMag)
-          mag += (fabs(d[0]) + fabs(d[1]) + fabs(d[2])) * (fabs(uu[0]) + fabs(uu[1]) + fabs(uu[2]));
-      });
+    for (int c = 0; c < 3; ++c) acc[3 * a + c] = ds[a] * mo.u[c] + mo.acc[3 * a + c];
+  if (kMag)
+    mag += mo.mag + (fabs(ds[0]) + fabs(ds[1]) + fabs(ds[2])) *
+                        (fabs(mo.u[0]) + fabs(mo.u[1]) + fabs(mo.u[2]));
   struct InE {
     R3<T> Ql, W;
   };
@@ -130,14 +176,15 @@ __device__ __forceinline__ A polar_gap(const A M[9], const A sig[3]) {
 // phase has them in registers).  P_i is kept when M_i = 0.
 template <typename T>
 __device__ void vertex_P_own(const DevChordal<T>& g, int i, const SweepParams& sp,
-                             const R3<T>& Qi, const P4<T>& si, const R3<T>& Pi, const R3<T>& Li) {
+                             const R3<T>& Qi, const P4<T>& ti, const P4<T>& si, const R3<T>& Pi,
+                             const R3<T>& Li, const MOut<T>* pre = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   T M[9], R[9], sig[3], mag = T(0);
-  p_matrix<T, T, kF32>(g, i, sp, Qi, si, Pi, Li, M, mag);
+  p_matrix<T, T, kF32>(g, i, sp, Qi, ti, si, Pi, Li, M, mag, pre);
   polar3<T>(M, R, sig);
   if (kF32 && !(polar_gap<T>(M, sig) >= T(1e-2) * mag)) {
     double Md[9], Rd[9], sd[3], dm = 0.0;
-    p_matrix<double, T, false>(g, i, sp, Qi, si, Pi, Li, Md, dm);
+    p_matrix<double, T, false>(g, i, sp, Qi, ti, si, Pi, Li, Md, dm);
     polar3<double>(Md, Rd, sd);
     if (sd[0] > 0.0 || sd[1] > 0.0 || sd[2] > 0.0) g.P[i] = st9<T, double>(Rd);
     return;
@@ -227,8 +274,12 @@ __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, int i, const Sw
 template <typename T>
 __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const SweepParams& sp,
                                          bool save, V3<T>& z, T cS, R3<T>* P_out = nullptr,
-                                         R3<T>* Q_out = nullptr, P4<T>* s_out = nullptr) {
+                                         R3<T>* Q_out = nullptr, P4<T>* t_out = nullptr,
+                                         P4<T>* s_out = nullptr, MOut<T>* mo = nullptr) {
+  constexpr bool kF32 = sizeof(T) == 4;
   const R3<T> Pi = g.P[i];
+  const P4<T> ti = g.t[i], si = g.s[i];
+  const T tiv[3] = {ti.x, ti.y, ti.z};
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
     P4<T> u, tj;
@@ -240,8 +291,8 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const Sw
         acc.x += x.u.u * x.tj.x - c.x;
         acc.y += x.u.u * x.tj.y - c.y;
         acc.z += x.u.u * x.tj.z - c.z;
+        if (mo) m_out_add<T, kF32>(*mo, tiv, x.tj, x.u);  // the next P's out-edge sum
       });
-  const P4<T> ti = g.t[i], si = g.s[i];
   const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);
   const T a = cS + b + h;
@@ -258,6 +309,7 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const Sw
   if (P_out) {
     *P_out = Pi;
     *Q_out = g.Q[i];
+    *t_out = ti;
     *s_out = pad3(sn);
   }
 }
@@ -265,7 +317,7 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const Sw
 template <int PH, typename T>
 __device__ __forceinline__ void phase_c(const DevChordal<T>& g, int i, const SweepParams& sp,
                                         bool save) {
-  if (PH == 0) vertex_P_own(g, i, sp, g.Q[i], g.s[i], g.P[i], g.L[i]);
+  if (PH == 0) vertex_P_own(g, i, sp, g.Q[i], g.t[i], g.s[i], g.P[i], g.L[i]);
   if (PH == 1) {
     R3<T> l = g.L[i];
     vertex_Q(g, i, sp, save, l, g.cQ[i]);
@@ -280,10 +332,12 @@ __device__ __forceinline__ void phase_c(const DevChordal<T>& g, int i, const Swe
   if (PH == 4) {  // S of this sweep + P of the next
     V3<T> z = v3(g.z[i]);
     R3<T> Pi, Qi;
-    P4<T> si;
-    vertex_S(g, i, sp, false, z, g.cS[i], &Pi, &Qi, &si);
+    P4<T> ti, si;
+    MOut<T> mo;
+    m_out_zero(mo);
+    vertex_S(g, i, sp, false, z, g.cS[i], &Pi, &Qi, &ti, &si, &mo);
     g.z[i] = pad3(z);
-    vertex_P_own(g, i, sp, Qi, si, Pi, g.L[i]);
+    vertex_P_own(g, i, sp, Qi, ti, si, Pi, g.L[i], &mo);
   }
 }
 
