@@ -132,8 +132,118 @@ __device__ void jacobi4(const double M[10], double w[4], double V[4][4]) {
   for (int k = 0; k < 4; ++k) w[k] = a[k][k];
 }
 
-// argmin over |x| = 1 of 1/2 x^T A x + b^T x (Lemma 1 / Lemma B.1), FP64
+// LDL^T of A + lam I (A symmetric, upper triangle in M); false unless every
+// pivot exceeds floor, i.e. unless A + lam I is safely positive definite.
+__device__ __forceinline__ bool ldl4(const double M[10], double lam, double floor,
+                                     double L[4][4], double dinv[4]) {
+  double d[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    double dj = M[uidx(j, j)] + lam;
+#pragma unroll
+    for (int k = 0; k < j; ++k) dj -= L[j][k] * L[j][k] * d[k];
+    if (!(dj > floor)) return false;
+    d[j] = dj;
+    dinv[j] = 1.0 / dj;
+#pragma unroll
+    for (int i = j + 1; i < 4; ++i) {
+      double sij = M[uidx(j, i)];
+#pragma unroll
+      for (int k = 0; k < j; ++k) sij -= L[i][k] * L[j][k] * d[k];
+      L[i][j] = sij * dinv[j];
+    }
+  }
+  return true;
+}
+
+// The easy case of Lemma B.1 (ii) without an eigen-decomposition: Newton on
+// phi(lambda) = 1/|x(lambda)| - 1, x(lambda) = -(A + lambda I)^{-1} b, each
+// step from an LDL^T factorisation (phi' = x^T (A + lambda I)^{-1} x /
+// |x|^3), started from the multiplier p^k would have (lambda = -p^T (A p + b)
+// at p = p^k, exact at a fixed point) and kept in a bracket [lo, hi] of the
+// root: lo = -min_k A_kk <= -a_min (a failed factorisation raises lo), hi =
+// |b| - (Gershgorin lower bound of a_min), where |x| <= 1.  phi is concave
+// and increasing on (-a_min, inf), so once left of the root Newton climbs to
+// it monotonically.  Returns false (the caller then takes the eigen-
+// decomposition path) on b = 0, a near-singular A + lambda I, or no
+// convergence: the root is unique on (-a_min, inf), so both paths give the
+// same point up to rounding.
+__device__ bool trs4_ldl(const double M[10], const double b[4], const double pprev[4],
+                         double x[4]) {
+  const double nb = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2] + b[3] * b[3]);
+  if (!(nb > 0.0)) return false;
+  double dmin = M[0], gmin = M[0], amax = fabs(M[0]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double off = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+      if (l != k) off += fabs(M[uidx(k < l ? k : l, k < l ? l : k)]);
+    const double dk = M[uidx(k, k)];
+    dmin = fmin(dmin, dk);
+    gmin = fmin(gmin, dk - off);
+    amax = fmax(amax, fabs(dk) + off);
+  }
+  const double floor = 1e-10 * fmax(1.0, fmax(amax, nb));
+  double lo = -dmin, hi = nb - gmin;
+  double Ap[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double sk = 0.0;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) sk += M[uidx(k < l ? k : l, k < l ? l : k)] * pprev[l];
+    Ap[k] = sk + b[k];
+  }
+  double lam = -(pprev[0] * Ap[0] + pprev[1] * Ap[1] + pprev[2] * Ap[2] + pprev[3] * Ap[3]);
+  if (!(lam > lo && lam < hi)) lam = hi;
+  for (int it = 0; it < 40; ++it) {
+    double L[4][4], dinv[4];
+    if (!ldl4(M, lam, floor, L, dinv)) {
+      lo = lam;  // not positive definite: lambda <= -a_min + floor
+      lam = 0.5 * (lo + hi);
+      continue;
+    }
+    double y[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {  // L y = -b
+      double yk = -b[k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) yk -= L[k][l] * y[l];
+      y[k] = yk;
+    }
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {  // L^T x = D^{-1} y
+      double xk = y[k] * dinv[k];
+#pragma unroll
+      for (int l = k + 1; l < 4; ++l) xk -= L[l][k] * x[l];
+      x[k] = xk;
+    }
+    double u[4], q = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {  // L u = x, q = u^T D^{-1} u
+      double uk = x[k];
+#pragma unroll
+      for (int l = 0; l < k; ++l) uk -= L[k][l] * u[l];
+      u[k] = uk;
+      q += uk * uk * dinv[k];
+    }
+    const double nx2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3];
+    const double nx = sqrt(nx2);
+    if (fabs(nx - 1.0) <= 1e-14) return true;
+    if (nx > 1.0) lo = lam; else hi = lam;
+    if (hi - lo <= 1e-15 * fmax(1.0, fabs(lam))) return false;
+    double next = lam + (nx - 1.0) * nx2 / q;
+    if (!(next > lo && next < hi)) next = 0.5 * (lo + hi);
+    lam = next;
+  }
+  return false;
+}
+
+// argmin over |x| = 1 of 1/2 x^T A x + b^T x (Lemma 1 / Lemma B.1), FP64:
+// the factorisation path above, else the eigen-decomposition of A (Newton
+// on the same phi with g = W^T b), which also covers the hard case.
 __device__ void trs4(const double M[10], const double b[4], const double pprev[4], double x[4]) {
+  if (trs4_ldl(M, b, pprev, x)) return;
   double w[4], V[4][4];
   jacobi4(M, w, V);
   int kmin = 0;
