@@ -64,15 +64,19 @@ def abar(g):
     return float(d.mean())
 
 
-KERNEL_SOURCES = ("sweep.hip", "chordal.hip", "qmath.hpp", "polar.hpp", "internal.hpp")
+KERNEL_SOURCES = {  # device sources each profiled sweep kernel is built from
+    "k_graph_sweeps_lds<float>": ("sweep.hip", "qmath.hpp", "internal.hpp"),
+    "k_graph_sweeps_c<float>": ("chordal.hip", "polar.hpp", "qmath.hpp", "internal.hpp"),
+    "k_graph_sweeps_a<float>": ("aniso.hip", "qmath.hpp", "internal.hpp"),
+}
 
 
-def source_sha():
-    """Hash of the device sources of the sweep kernels (the byte counters of
-    profiles/traffic.json hold only for the kernels they were taken on)."""
+def source_sha(kernel):
+    """Hash of a sweep kernel's device sources (the byte counters of
+    profiles/traffic.json hold only for the kernel they were taken on)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2601_15684_amd", "csrc")
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES.get(kernel, ()):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -86,7 +90,7 @@ def load_traffic(kernel):
         rec = json.load(open(path))[kernel]
     except (OSError, KeyError, ValueError):
         return None
-    if rec.get("source_sha") != source_sha():
+    if kernel not in KERNEL_SOURCES or rec.get("source_sha") != source_sha(kernel):
         return None
     return rec["bytes_per_launch"]
 
@@ -373,13 +377,13 @@ def main():
                        args.block, epg, model="chordal")
         cb = (B_EDGE_CHORDAL * m + B_VERTEX_CHORDAL * n) * args.sweeps
         ca = cb / (rc["kern_ms"] * 1e-3) / 1e9
+        ckern = "k_graph_sweeps_c<float>" if rc["info"]["schedule"] == 2 else "k_phase_c<*,float>"
         out["chordal"] = {
             "value": rc["edge_iters"] / rc["wall"] if stc else None, "unit": "edge-iter/s",
-            "steps": stc, "dtype": "f32", "kernel": "k_graph_sweeps_c<float>"
-            if rc["info"]["schedule"] == 2 else "k_phase_c<*,float>",
+            "steps": stc, "dtype": "f32", "kernel": ckern,
             "kernel_ms_per_launch": rc["kern_ms"],
             "roofline": {"bound": "hbm", "achieved": ca, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ca / HBM_PEAK_GBS, "traffic": load_traffic("k_graph_sweeps_c<float>"),
+                         "frac": ca / HBM_PEAK_GBS, "traffic": load_traffic(ckern),
                          "bytes_model": f"{B_EDGE_CHORDAL} B/edge + {B_VERTEX_CHORDAL} B/pose per "
                                         f"sweep x {args.sweeps} sweeps"},
             "batch_health": health(rc, betas)}
@@ -395,13 +399,13 @@ def main():
         del info
         ib = (B_EDGE_INFO * m + B_VERTEX * n) * args.sweeps
         ia = ib / (ri["kern_ms"] * 1e-3) / 1e9
+        ikern = "k_graph_sweeps_a<float>" if ri["info"]["schedule"] == 2 else "k_phase_a<*,float>"
         out["information_model"] = {
             "value": ri["edge_iters"] / ri["wall"] if sti else None, "unit": "edge-iter/s",
-            "steps": sti, "dtype": "f32",
-            "kernel": ("k_graph_sweeps_a<float>" if ri["info"]["schedule"] == 2 else "k_phase_a<*,float>"),
+            "steps": sti, "dtype": "f32", "kernel": ikern,
             "kernel_ms_per_launch": ri["kern_ms"],
             "roofline": {"bound": "hbm", "achieved": ia, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ia / HBM_PEAK_GBS,
+                         "frac": ia / HBM_PEAK_GBS, "traffic": load_traffic(ikern),
                          "bytes_model": f"{B_EDGE_INFO} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps"},
             "batch_health": health(ri, betas)}
     if not args.skip_cinit:

@@ -377,25 +377,34 @@ __device__ void vertex_P_own(const DevAniso<T>& a, int i, const SweepParams& sp,
   A M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   A bv[4] = {0, 0, 0, 0};
   A diag = A(sp.beta) + A(sp.h1);
-  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
-    const P4<T> tt = g.o_tt[e];
-    const P4<T> tj = g.t[g.o_nbr[e]];
-    const Sym3<A> S = sym3<A>(a.o_Sa[e], a.o_Sb[e]);
-    const V3<A> tm = {A(tt.x), A(tt.y), A(tt.z)};
-    const Q4<A> u = qmul_pure_r(qi, tm);  // q_i (x) [0, t~]
-    Q4<A> c[4];
-    cols_right(u, c);
-    const V3<A> Sr = smul(S, V3<A>{A(tj.x) - si.x, A(tj.y) - si.y, A(tj.z) - si.z});
-    add_quadratic(c, A(tt.u), S, Sr, M, bv, A(-1));
-  }
-  for (int e = g.i_ptr[i]; e < g.i_ptr[i + 1]; ++e) {
-    const Q4<A> ql = cvt<A>(g.q[g.i_nbr[e]]);
-    const Q4<A> w = cvt<A>(g.i_w[e]);
-    const A kap = sqrt(w.w * w.w + w.x * w.x + w.y * w.y + w.z * w.z);
-    diag += A(2) * kap * (ql.w * ql.w + ql.x * ql.x + ql.y * ql.y + ql.z * ql.z);
-    const Q4<A> t = qmul(ql, w);
-    bv[0] -= A(2) * t.w; bv[1] -= A(2) * t.x; bv[2] -= A(2) * t.y; bv[3] -= A(2) * t.z;
-  }
+  struct OutE {
+    P4<T> tt, tj, Sa, Sb;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1],
+      [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]], a.o_Sa[e], a.o_Sb[e]}; },
+      [&](const OutE& d) {
+        const Sym3<A> S = sym3<A>(d.Sa, d.Sb);
+        const V3<A> tm = {A(d.tt.x), A(d.tt.y), A(d.tt.z)};
+        const Q4<A> u = qmul_pure_r(qi, tm);  // q_i (x) [0, t~]
+        Q4<A> c[4];
+        cols_right(u, c);
+        const V3<A> Sr = smul(S, V3<A>{A(d.tj.x) - si.x, A(d.tj.y) - si.y, A(d.tj.z) - si.z});
+        add_quadratic(c, A(d.tt.u), S, Sr, M, bv, A(-1));
+      });
+  struct InE {
+    Q4<T> ql, w;
+  };
+  edge_loop(
+      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{g.q[g.i_nbr[e]], g.i_w[e]}; },
+      [&](const InE& d) {
+        const Q4<A> ql = cvt<A>(d.ql);
+        const Q4<A> w = cvt<A>(d.w);
+        const A kap = sqrt(w.w * w.w + w.x * w.x + w.y * w.y + w.z * w.z);
+        diag += A(2) * kap * (ql.w * ql.w + ql.x * ql.x + ql.y * ql.y + ql.z * ql.z);
+        const Q4<A> t = qmul(ql, w);
+        bv[0] -= A(2) * t.w; bv[1] -= A(2) * t.x; bv[2] -= A(2) * t.y; bv[3] -= A(2) * t.z;
+      });
   M[0] += diag; M[4] += diag; M[7] += diag; M[9] += diag;
   const Q4<A> li = cvt<A>(li_), pi = cvt<A>(pi_);
   const A b = A(sp.beta), h = A(sp.h1);
@@ -419,23 +428,29 @@ __device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, int i, const Swee
   T M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   T bv[4] = {0, 0, 0, 0};
   T diag = T(sp.beta) + T(sp.h2);
-  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
-    const int j = g.o_nbr[e];
-    const P4<T> tt = g.o_tt[e];
-    const V3<T> tj = v3(g.t[j]);
-    const Sym3<T> S = sym3<T>(a.o_Sa[e], a.o_Sb[e]);
-    const Q4<T> v = qmul_pv(V3<T>{tt.x, tt.y, tt.z}, pic);  // [0, t~] (x) p_i^*
-    Q4<T> c[4];
-    cols_left(v, c);
-    const V3<T> Sr = smul(S, V3<T>{tj.x - si.x, tj.y - si.y, tj.z - si.z});
-    add_quadratic(c, tt.u, S, Sr, M, bv, T(1));
-    const Q4<T> pj = g.p[j];
-    const Q4<T> w = g.o_w[e];
-    const T kap = sqrt(w.w * w.w + w.x * w.x + w.y * w.y + w.z * w.z);
-    diag += T(2) * kap * (pj.w * pj.w + pj.x * pj.x + pj.y * pj.y + pj.z * pj.z);
-    const Q4<T> t = qmul(pj, qconj(w));
-    bv[0] += T(2) * t.w; bv[1] += T(2) * t.x; bv[2] += T(2) * t.y; bv[3] += T(2) * t.z;
-  }
+  struct OutE {
+    P4<T> tt, tj, Sa, Sb;
+    Q4<T> pj, w;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1],
+      [&](int e) {
+        const int j = g.o_nbr[e];
+        return OutE{g.o_tt[e], g.t[j], a.o_Sa[e], a.o_Sb[e], g.p[j], g.o_w[e]};
+      },
+      [&](const OutE& d) {
+        const Sym3<T> S = sym3<T>(d.Sa, d.Sb);
+        const Q4<T> v = qmul_pv(V3<T>{d.tt.x, d.tt.y, d.tt.z}, pic);  // [0, t~] (x) p_i^*
+        Q4<T> c[4];
+        cols_left(v, c);
+        const V3<T> Sr = smul(S, V3<T>{d.tj.x - si.x, d.tj.y - si.y, d.tj.z - si.z});
+        add_quadratic(c, d.tt.u, S, Sr, M, bv, T(1));
+        const Q4<T> pj = d.pj, w = d.w;
+        const T kap = sqrt(w.w * w.w + w.x * w.x + w.y * w.y + w.z * w.z);
+        diag += T(2) * kap * (pj.w * pj.w + pj.x * pj.x + pj.y * pj.y + pj.z * pj.z);
+        const Q4<T> t = qmul(pj, qconj(w));
+        bv[0] += T(2) * t.w; bv[1] += T(2) * t.x; bv[2] += T(2) * t.y; bv[3] += T(2) * t.z;
+      });
   M[0] += diag; M[4] += diag; M[7] += diag; M[9] += diag;
   const T b = T(sp.beta), h = T(sp.h2);
   bv[0] += b * pi.w - li.w + h * qi.w;
@@ -460,14 +475,22 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, int i, const Swee
                                          bool save, const V3<T>& zi) {
   const DevGraph<T>& g = a.g;
   V3<T> acc = {T(0), T(0), T(0)};
-  for (int e = g.i_ptr[i]; e < g.i_ptr[i + 1]; ++e) {
-    const int l = g.i_nbr[e];
-    const P4<T> tt = g.i_tt[e];
-    const V3<T> sl = v3(g.s[l]);
-    const V3<T> c = im_mul_conj(qmul_vp(g.q[l], V3<T>{tt.x, tt.y, tt.z}), g.p[l]);
-    const V3<T> y = smul(sym3<T>(a.i_Sa[e], a.i_Sb[e]), V3<T>{sl.x + c.x, sl.y + c.y, sl.z + c.z});
-    acc.x += y.x; acc.y += y.y; acc.z += y.z;
-  }
+  struct InE {
+    P4<T> tt, sl, Sa, Sb;
+    Q4<T> ql, pl;
+  };
+  edge_loop(
+      g.i_ptr[i], g.i_ptr[i + 1],
+      [&](int e) {
+        const int l = g.i_nbr[e];
+        return InE{g.i_tt[e], g.s[l], a.i_Sa[e], a.i_Sb[e], g.q[l], g.p[l]};
+      },
+      [&](const InE& d) {
+        const V3<T> c = im_mul_conj(qmul_vp(d.ql, V3<T>{d.tt.x, d.tt.y, d.tt.z}), d.pl);
+        const V3<T> y =
+            smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.sl.x + c.x, d.sl.y + c.y, d.sl.z + c.z});
+        acc.x += y.x; acc.y += y.y; acc.z += y.z;
+      });
   const P4<T> ti = g.t[i], si = g.s[i];
   const T b = T(sp.beta), h = T(sp.h3);
   const V3<T> rhs = {T(2) * acc.x + b * si.x + zi.x + h * ti.x, T(2) * acc.y + b * si.y + zi.y + h * ti.y,
@@ -483,13 +506,18 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, int i, const Swee
   const DevGraph<T>& g = a.g;
   const Q4<T> pi = g.p[i], qi = g.q[i];
   V3<T> acc = {T(0), T(0), T(0)};
-  for (int e = g.o_ptr[i]; e < g.o_ptr[i + 1]; ++e) {
-    const P4<T> tt = g.o_tt[e];
-    const V3<T> tj = v3(g.t[g.o_nbr[e]]);
-    const V3<T> c = im_mul_conj(qmul_vp(qi, V3<T>{tt.x, tt.y, tt.z}), pi);
-    const V3<T> y = smul(sym3<T>(a.o_Sa[e], a.o_Sb[e]), V3<T>{tj.x - c.x, tj.y - c.y, tj.z - c.z});
-    acc.x += y.x; acc.y += y.y; acc.z += y.z;
-  }
+  struct OutE {
+    P4<T> tt, tj, Sa, Sb;
+  };
+  edge_loop(
+      g.o_ptr[i], g.o_ptr[i + 1],
+      [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]], a.o_Sa[e], a.o_Sb[e]}; },
+      [&](const OutE& d) {
+        const V3<T> c = im_mul_conj(qmul_vp(qi, V3<T>{d.tt.x, d.tt.y, d.tt.z}), pi);
+        const V3<T> y =
+            smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.tj.x - c.x, d.tj.y - c.y, d.tj.z - c.z});
+        acc.x += y.x; acc.y += y.y; acc.z += y.z;
+      });
   const P4<T> ti = g.t[i], si = g.s[i];
   const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);

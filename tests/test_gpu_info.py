@@ -143,3 +143,38 @@ def test_solve_and_unsupported_calls(pgo):
         with pytest.raises(pgo.PgoError) as ex:
             pgo.pgo_forward_record(h.h, 3, 1.0, GAMMA, 1)
         assert ex.value.name == "PGO_ESTATE"
+
+
+def scrambled_state(g, beta, seed):
+    """A state far from every subproblem's solution: random unit p, q near
+    p, positions and splits off the initial ones, multipliers of size beta."""
+    rng = np.random.default_rng(seed)
+    p = rng.standard_normal((g.n, 4))
+    p /= np.linalg.norm(p, axis=1, keepdims=True)
+    q = p + 0.3 * rng.standard_normal((g.n, 4))
+    t = g.t0 + rng.standard_normal((g.n, 3))
+    s = t + 0.5 * rng.standard_normal((g.n, 3))
+    lam = beta * rng.standard_normal((g.n, 4))
+    z = beta * rng.standard_normal((g.n, 3))
+    return np.concatenate([p, q, t, s, lam, z], 1)
+
+
+@pytest.mark.parametrize("name,aniso", CASES)
+@pytest.mark.parametrize("beta_scale", [0.01, 1.0])
+def test_p_update_from_scrambled_states(pgo, name, aniso, beta_scale):
+    """The sphere-constrained p update warm-starts its multiplier from p^k; a
+    random p^k makes it leave that start (bracketing, bisection, and the
+    eigen-decomposition fallback where the factorisation path gives up)."""
+    g = S.make_config(name)
+    info = S.random_info(g.m, g.tau, aniso, seed=5)
+    beta = beta_scale * abar(g)
+    st0 = scrambled_state(g, beta, seed=6)
+    P, _, _ = A.prepare(g.n, g.ei, g.ej, g.Rm, g.tm, g.kappa, info, g.R0, g.t0)
+    cols = dict(p=(0, 4), q=(4, 8), t=(8, 11), s=(11, 14), lam=(14, 18), z=(18, 21))
+    ost = {k: torch.tensor(st0[:, a:b]) for k, (a, b) in cols.items()}
+    ref = A.iterate(P, ost, 3, beta, GAMMA)
+    with pgo.PoseGraph.from_graph(g, info=info, precision="fp64") as h:
+        h.set_state(st0)
+        h.iterate(3, beta, GAMMA)
+        got = h.state()
+    assert_parity(scaled_err(got, pack(ref), beta), 1e-10, f"{name}/beta x{beta_scale}")
