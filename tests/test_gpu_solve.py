@@ -103,3 +103,26 @@ def test_solve_argument_checks(pgo):
                      (100, 50, GAMMA, 0.0, 0.5, 1.0), (100, 50, GAMMA, 0.0, 2.0, -1.0)):
             with pytest.raises(pgo.PgoError):
                 pgo.pgo_solve(h.h, *args)
+
+
+def test_reaches_the_oracle_minimum(pgo):
+    """grid-1k from its odometry start: the sweeps reach the minimum of model
+    (1) that the oracle's least squares found (tests/golden/fstar_grid1k.json,
+    written by tests/golden/make_fstar.py) to 1e-6 relative, and no iterate's
+    cost falls below it."""
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fstar_grid1k.json")
+    F_star = json.load(open(path))["F_star"]
+    g = S.make_config("grid-1k")
+    beta = 0.01 * abar(g)
+    for prec, floor in (("fp64", 1e-9), ("fp32", 1e-6)):
+        with pgo.PoseGraph.from_graph(g, precision=prec) as h:
+            best = np.inf
+            for _ in range(30):
+                h.iterate(100, beta, GAMMA)
+                F = h.cost()[0]
+                assert F >= F_star * (1 - floor), (prec, F, F_star)
+                best = min(best, F)
+        assert best <= F_star * (1 + 1e-6), (prec, best, F_star)
