@@ -65,7 +65,7 @@ def abar(g):
 
 
 KERNEL_SOURCES = {  # device sources each profiled sweep kernel is built from
-    "k_graph_sweeps_lds<float>": ("sweep.hip", "qmath.hpp", "internal.hpp"),
+    "k_graph_sweeps<float>": ("sweep.hip", "qmath.hpp", "internal.hpp"),
     "k_graph_sweeps_c<float>": ("chordal.hip", "polar.hpp", "qmath.hpp", "internal.hpp"),
     "k_graph_sweeps_a<float>": ("aniso.hip", "qmath.hpp", "internal.hpp"),
 }
@@ -329,7 +329,7 @@ def main():
     algo_bytes = (B_EDGE * m + B_VERTEX * n) * args.sweeps
     achieved = algo_bytes / (r32["kern_ms"] * 1e-3) / 1e9
     phase_bytes = (B_EDGE_PHASE * m + B_VERTEX_PHASE * n) * args.sweeps
-    kname = (("k_graph_sweeps_lds<float>" if r32["info"]["lds"] else "k_graph_sweeps<float>")
+    kname = ("k_graph_sweeps<float>"
              if r32["info"]["schedule"] == 2 else "k_phase<*,float>")
     out = {
         "metric": "edge-iters/s + time to 1e-6 rel cost; FP32/batched vs plain FP64, 1 GPU",
@@ -347,7 +347,7 @@ def main():
         "config": {"workload": "batched-4096", "graphs": args.graphs, "poses": n, "edges": m,
                    "sweeps_per_step": args.sweeps, "beta": f"{BETA_SCALE} x mean diagonal weight, per graph",
                    "gamma": GAMMA, "schedule": ["auto", "phase", "graph"][r32["info"]["schedule"]],
-                   "block": r32["info"]["block"], "lds_multipliers": bool(r32["info"]["lds"]),
+                   "block": r32["info"]["block"], "lds_state": bool(r32["info"]["lds"]),
                    "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname),

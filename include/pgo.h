@@ -251,15 +251,16 @@ pgo_status pgo_set_state(pgo_graph* g, const double* state);
 pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat0);
 
 /* Sizes and settings of the handle; any pointer may be NULL.  lds = 1 when
- * the per-graph schedule keeps every vertex's multipliers in LDS for the
- * whole launch (quaternion model, 8 words x the largest graph's vertex
- * count within 160 KiB, chosen by default or by the autotuner). */
+ * the per-graph schedule keeps each graph's state in LDS for the whole
+ * launch as far as it fits (quaternion model: p and q, then t and s, then
+ * the multipliers, by graph size, within 160 KiB per workgroup; chosen by
+ * default or by the autotuner). */
 pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
                     int32_t* schedule, int32_t* block, int32_t* model, int32_t* lds);
 
 /*
  * pgo_autotune -- time the candidate schedules, workgroup sizes and (per-
- * graph schedule) LDS residency of the multipliers on this handle's own
+ * graph schedule) LDS residency of the state on this handle's own
  * graphs (sweeps sweeps each, beta, gamma), keep the fastest for later
  * pgo_iterate calls, and restore the state it found.  Reports the choice
  * through pgo_info.

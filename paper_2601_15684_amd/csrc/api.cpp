@@ -98,7 +98,7 @@ struct pgo_graph {
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
-  int graph_lds = 1;  // per-graph kernel keeps lambda and z in LDS when they fit
+  int graph_lds = 1;  // per-graph kernel keeps graphs' state in LDS (quaternion model)
   bool have_prev = false;
   // captured launch sequence of the per-phase schedule
   hipGraphExec_t gexec = nullptr;
@@ -203,12 +203,10 @@ DevChordal<T> viewc(const pgo_graph* g) {
   return d;
 }
 
-// Whether the quaternion per-graph kernel can hold every vertex's lambda and
-// z in LDS (the rule of launch_graph_sweeps: (4 + 4) words x max_n <= 160 KiB).
-bool lds_fits(const pgo_graph* g) {
-  const size_t w = g->opt.precision == PGO_FP64 ? 8 : 4;
-  return !g->chordal && !g->aniso && 8 * w * size_t(g->max_n) <= 160 * 1024;
-}
+// Whether the per-graph kernel can keep graphs' state in LDS for a launch
+// (the quaternion model; each graph takes the largest residency tier that
+// fits, see launch_graph_sweeps).
+bool lds_fits(const pgo_graph* g) { return !g->chordal && !g->aniso; }
 
 template <typename T>
 DevAniso<T> viewa(const pgo_graph* g) {

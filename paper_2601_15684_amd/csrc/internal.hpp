@@ -94,8 +94,9 @@ struct DevChordal {
 template <typename T>
 hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& sp, int block,
                                hipStream_t st);
-// lds != 0 selects the variant that holds every vertex's lambda and z in LDS
-// for the whole launch (when max_n slots fit in 160 KB).
+// lds != 0 lets every graph keep the part of its state that fits in LDS
+// there for the whole launch (p, q; then t, s; then lambda, z, by graph
+// size; at most 160 KiB per workgroup); lds == 0 keeps it all in memory.
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
                                int G, int k, const SweepParams& sp, int block, int max_n, int lds,

@@ -35,6 +35,8 @@
 // several, and the compiler's choice of fused multiply-adds depends on the
 // code around an expression.
 #pragma clang fp contract(off)
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace pgo {
@@ -96,12 +98,37 @@ __device__ __forceinline__ Q4<A> p_out_finish(const POut<A>& po, const Q4<A>& qi
   return {head.w + po.x.w, head.x + po.x.x, head.y + po.x.y, head.z + po.x.z};
 }
 
+// Where the state of the vertices being updated lives: each array either
+// in global memory (base 0) or, in the per-graph kernel, in LDS for the
+// graph's vertices v0.. (base v0); element j of an array is x[j - xb].
+template <typename T>
+struct State {
+  Q4<T>* p_;
+  Q4<T>* q_;
+  P4<T>* t_;
+  P4<T>* s_;
+  Q4<T>* lam_;
+  P4<T>* z_;
+  int pb, qb, tb, sb, lb, zb;
+  __device__ __forceinline__ Q4<T>& p(int j) const { return p_[j - pb]; }
+  __device__ __forceinline__ Q4<T>& q(int j) const { return q_[j - qb]; }
+  __device__ __forceinline__ P4<T>& t(int j) const { return t_[j - tb]; }
+  __device__ __forceinline__ P4<T>& s(int j) const { return s_[j - sb]; }
+  __device__ __forceinline__ Q4<T>& lam(int j) const { return lam_[j - lb]; }
+  __device__ __forceinline__ P4<T>& z(int j) const { return z_[j - zb]; }
+};
+
+template <typename T>
+__device__ __forceinline__ State<T> global_state(const DevGraph<T>& g) {
+  return {g.p, g.q, g.t, g.s, g.lam, g.z, 0, 0, 0, 0, 0, 0};
+}
+
 // Sum of the edge terms of the P phase, in accumulation type A; the
 // out-edge part is taken from pre when the caller gathered it already.
 template <typename A, typename T, bool kMag>
-__device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, const Q4<T>& q_i,
-                                            const P4<T>& t_i, const P4<T>& s_i, A& mag,
-                                            const POut<A>* pre = nullptr) {
+__device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, const State<T>& st, int i,
+                                            const Q4<T>& q_i, const P4<T>& t_i, const P4<T>& s_i,
+                                            A& mag, const POut<A>* pre = nullptr) {
   const Q4<A> qi = cvt<A>(q_i);
   const V3<A> ti = v3a<A>(t_i);
   POut<A> po;
@@ -113,7 +140,7 @@ __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, const Q
       P4<T> tj, u;
     };
     edge_loop(
-        g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
+        g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{st.t(g.o_nbr[e]), g.o_tt[e]}; },
         [&](const OutE& d) { p_out_add<A, kMag>(po, qi, ti, d.tj, d.u); });
   }
   Q4<A> acc = p_out_finish<A, kMag>(po, qi, ti, v3a<A>(s_i), mag);
@@ -121,7 +148,7 @@ __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, int i, const Q
     Q4<T> ql, w;
   };
   edge_loop(
-      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{g.q[g.i_nbr[e]], g.i_w[e]}; },
+      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{st.q(g.i_nbr[e]), g.i_w[e]}; },
       [&](const InE& d) {
         const Q4<A> term = qmul(cvt<A>(d.ql), cvt<A>(d.w));
         acc4(acc, term);
@@ -139,21 +166,17 @@ __device__ __forceinline__ Q4<A> p_vector(const Q4<A>& acc, const Q4<T>& q_i, co
           A(2) * acc.y + b * qi.y + li.y + h * pi.y, A(2) * acc.z + b * qi.z + li.z + h * pi.z};
 }
 
-// The own-only values of a vertex (never read by a neighbour): the
-// multipliers lambda_i, z_i and the constants cQ_i, cT_i, cS_i.  They are
-// passed in by the caller, which keeps them in memory (per-phase launches)
-// or in registers across all sweeps of a launch (per-graph kernel).
 // P update of vertex i from its own values q_i, t_i, s_i, p_i, lambda_i
 // (passed in, so a caller that has them in registers does not reload them)
 // and, from the fused S+P phase, the out-edge sum S gathered.
 template <typename T>
-__device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                             const Q4<T>& qi, const P4<T>& ti, const P4<T>& si,
-                                             const Q4<T>& pi, const Q4<T>& li,
-                                             const POut<T>* pre = nullptr) {
+__device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, const State<T>& st, int i,
+                                             const SweepParams& sp, const Q4<T>& qi,
+                                             const P4<T>& ti, const P4<T>& si, const Q4<T>& pi,
+                                             const Q4<T>& li, const POut<T>* pre = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   T mag = T(0);
-  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, i, qi, ti, si, mag, pre);
+  const Q4<T> acc = p_edge_sum<T, T, kF32>(g, st, i, qi, ti, si, mag, pre);
   const Q4<T> v = p_vector<T, T>(acc, qi, pi, li, sp);
   const T nrm = sqrt(v.w * v.w + v.x * v.x + v.y * v.y + v.z * v.z);
   if (kF32) {
@@ -161,28 +184,28 @@ __device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, int i, const 
     const T tot = T(2) * mag + T(sp.beta) * l1(qi) + l1(li) + T(sp.h1) * l1(pi);
     if (!(nrm >= T(1e-3) * tot)) {
       double dm = 0.0;
-      const Q4<double> dacc = p_edge_sum<double, T, false>(g, i, qi, ti, si, dm);
+      const Q4<double> dacc = p_edge_sum<double, T, false>(g, st, i, qi, ti, si, dm);
       const Q4<double> dv = p_vector<double, T>(dacc, qi, pi, li, sp);
       const double dn = sqrt(dv.w * dv.w + dv.x * dv.x + dv.y * dv.y + dv.z * dv.z);
       if (dn > 0.0)
-        g.p[i] = Q4<T>{T(dv.w / dn), T(dv.x / dn), T(dv.y / dn), T(dv.z / dn)};
+        st.p(i) = Q4<T>{T(dv.w / dn), T(dv.x / dn), T(dv.y / dn), T(dv.z / dn)};
       return;
     }
   }
-  if (nrm > T(0)) g.p[i] = Q4<T>{v.w / nrm, v.x / nrm, v.y / nrm, v.z / nrm};
+  if (nrm > T(0)) st.p(i) = Q4<T>{v.w / nrm, v.x / nrm, v.y / nrm, v.z / nrm};
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_P(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         const Q4<T>& li) {
-  vertex_P_own(g, i, sp, g.q[i], g.t[i], g.s[i], g.p[i], li);
+__device__ __forceinline__ void vertex_P(const DevGraph<T>& g, const State<T>& st, int i,
+                                         const SweepParams& sp) {
+  vertex_P_own(g, st, i, sp, st.q(i), st.t(i), st.s(i), st.p(i), st.lam(i));
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         bool save, Q4<T>& lam, T cQ) {
-  const Q4<T> pi = g.p[i], qi = g.q[i], li = lam;
-  const V3<T> si = v3(g.s[i]);
+__device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const State<T>& st, int i,
+                                         const SweepParams& sp, bool save) {
+  const Q4<T> pi = st.p(i), qi = st.q(i), li = st.lam(i);
+  const V3<T> si = v3(st.s(i));
   Q4<T> acc = {T(0), T(0), T(0), T(0)};
   struct OutE {
     P4<T> tj, u;
@@ -192,7 +215,7 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const Swee
       g.o_ptr[i], g.o_ptr[i + 1],
       [&](int e) {
         const int j = g.o_nbr[e];
-        return OutE{g.t[j], g.o_tt[e], g.p[j], g.o_w[e]};
+        return OutE{st.t(j), g.o_tt[e], st.p(j), g.o_w[e]};
       },
       [&](const OutE& d) {
         const V3<T> tj = v3(d.tj);
@@ -202,7 +225,7 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const Swee
         acc4(acc, qmul(d.pj, qconj(d.w)));
       });
   const T b = T(sp.beta), h = T(sp.h2);
-  const T a = cQ + b + h;
+  const T a = g.cQ[i] + b + h;
   const Q4<T> qn = {(T(2) * acc.w + b * pi.w - li.w + h * qi.w) / a,
                     (T(2) * acc.x + b * pi.x - li.x + h * qi.x) / a,
                     (T(2) * acc.y + b * pi.y - li.y + h * qi.y) / a,
@@ -212,14 +235,14 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, int i, const Swee
     g.q_prev[i] = qi;
     g.lam_prev[i] = li;
   }
-  g.q[i] = qn;
-  lam = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x), li.y - gb * (pi.y - qn.y),
-              li.z - gb * (pi.z - qn.z)};
+  st.q(i) = qn;
+  st.lam(i) = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x),
+                    li.y - gb * (pi.y - qn.y), li.z - gb * (pi.z - qn.z)};
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         bool save, const V3<T>& zi, T cT) {
+__device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const State<T>& st, int i,
+                                         const SweepParams& sp, bool save) {
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
     P4<T> u, sl;
@@ -229,7 +252,7 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const Swee
       g.i_ptr[i], g.i_ptr[i + 1],
       [&](int e) {
         const int l = g.i_nbr[e];
-        return InE{g.i_tt[e], g.s[l], g.q[l], g.p[l]};
+        return InE{g.i_tt[e], st.s(l), st.q(l), st.p(l)};
       },
       [&](const InE& d) {
         const V3<T> c = im_mul_conj(qmul_vp(d.ql, v3(d.u)), d.pl);  // Im(q_l [0,tau t~] p_l^*)
@@ -237,30 +260,34 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, int i, const Swee
         acc.y += d.u.u * d.sl.y + c.y;
         acc.z += d.u.u * d.sl.z + c.z;
       });
-  const P4<T> ti = g.t[i], si = g.s[i];
+  const P4<T> ti = st.t(i), si = st.s(i), zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h3);
-  const T a = cT + b + h;
+  const T a = g.cT[i] + b + h;
   if (save) g.t_prev[i] = ti;
-  g.t[i] = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
-                 (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
-                 (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
+  st.t(i) = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+                  (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
+                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
 }
 
+// S update of vertex i; with po, the same pass over the out-edges also
+// gathers the next P's out-edge sum, and the vertex's own values are handed
+// over in pi, qi, ti, si_new.
 template <typename T>
-__device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                         bool save, V3<T>& z, T cS, Q4<T>* p_out = nullptr,
+__device__ __forceinline__ void vertex_S(const DevGraph<T>& g, const State<T>& st, int i,
+                                         const SweepParams& sp, bool save,
+                                         POut<T>* po = nullptr, Q4<T>* p_out = nullptr,
                                          Q4<T>* q_out = nullptr, P4<T>* t_out = nullptr,
-                                         P4<T>* s_out = nullptr, POut<T>* po = nullptr) {
+                                         P4<T>* s_out = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
-  const Q4<T> pi = g.p[i], qi = g.q[i];
-  const P4<T> ti = g.t[i], si = g.s[i];
+  const Q4<T> pi = st.p(i), qi = st.q(i);
+  const P4<T> ti = st.t(i), si = st.s(i);
   const V3<T> tiv = v3(ti);
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
     P4<T> u, tj;
   };
   edge_loop(
-      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]]}; },
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e])}; },
       [&](const OutE& d) {
         const V3<T> c = im_mul_conj(qmul_vp(qi, v3(d.u)), pi);  // Im(q_i [0,tau t~] p_i^*)
         acc.x += d.u.u * d.tj.x - c.x;
@@ -268,9 +295,9 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
         acc.z += d.u.u * d.tj.z - c.z;
         if (po) p_out_add<T, kF32>(*po, qi, tiv, d.tj, d.u);  // the next P's out-edge sum
       });
-  const V3<T> zi = z;
+  const V3<T> zi = v3(st.z(i));
   const T b = T(sp.beta), h = T(sp.h4);
-  const T a = cS + b + h;
+  const T a = g.cS[i] + b + h;
   const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
                     (T(2) * acc.y + b * ti.y - zi.y + h * si.y) / a,
                     (T(2) * acc.z + b * ti.z - zi.z + h * si.z) / a};
@@ -279,8 +306,9 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
     g.s_prev[i] = si;
     g.z_prev[i] = pad3(zi);
   }
-  g.s[i] = pad3(sn);
-  z = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  st.s(i) = pad3(sn);
+  st.z(i) = pad3(V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
+                       zi.z - gb * (ti.z - sn.z)});
   if (p_out) {
     *p_out = pi;
     *q_out = qi;
@@ -294,36 +322,24 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, int i, const Swee
 // is needed between them; P reuses S's own values and the out-edge sum S
 // gathered in its pass, so the out-edges are read once for both.
 template <typename T>
-__device__ __forceinline__ void vertex_SP(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                          V3<T>& z, T cS, const Q4<T>& li) {
+__device__ __forceinline__ void vertex_SP(const DevGraph<T>& g, const State<T>& st, int i,
+                                          const SweepParams& sp) {
   Q4<T> pi, qi;
   P4<T> ti, si;
   POut<T> po = p_out_zero<T>();
-  vertex_S(g, i, sp, false, z, cS, &pi, &qi, &ti, &si, &po);
-  vertex_P_own(g, i, sp, qi, ti, si, pi, li, &po);
+  vertex_S(g, st, i, sp, false, &po, &pi, &qi, &ti, &si);
+  vertex_P_own(g, st, i, sp, qi, ti, si, pi, st.lam(i), &po);
 }
 
-// phase bodies with the own-only values kept in memory
+// phase bodies: 0 P, 1 Q, 2 T, 3 S, 4 S of this sweep + P of the next
 template <int PH, typename T>
-__device__ __forceinline__ void phase_mem(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                          bool save) {
-  if (PH == 0) vertex_P(g, i, sp, g.lam[i]);
-  if (PH == 1) {
-    Q4<T> l = g.lam[i];
-    vertex_Q(g, i, sp, save, l, g.cQ[i]);
-    g.lam[i] = l;
-  }
-  if (PH == 2) vertex_T(g, i, sp, save, v3(g.z[i]), g.cT[i]);
-  if (PH == 3) {
-    V3<T> z = v3(g.z[i]);
-    vertex_S(g, i, sp, save, z, g.cS[i]);
-    g.z[i] = pad3(z);
-  }
-  if (PH == 4) {  // S of this sweep + P of the next
-    V3<T> z = v3(g.z[i]);
-    vertex_SP(g, i, sp, z, g.cS[i], g.lam[i]);
-    g.z[i] = pad3(z);
-  }
+__device__ __forceinline__ void phase(const DevGraph<T>& g, const State<T>& st, int i,
+                                      const SweepParams& sp, bool save) {
+  if (PH == 0) vertex_P(g, st, i, sp);
+  if (PH == 1) vertex_Q(g, st, i, sp, save);
+  if (PH == 2) vertex_T(g, st, i, sp, save);
+  if (PH == 3) vertex_S(g, st, i, sp, save);
+  if (PH == 4) vertex_SP(g, st, i, sp);
 }
 
 // ---------------------------------------------------------------------------
@@ -347,7 +363,7 @@ __global__ void k_phase(DevGraph<T> g, SweepParams sp, int save) {
   if (i >= g.n) return;
   if (sp.active && !sp.active[g.gid[i]]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[g.gid[i]];
-  phase_mem<PH, T>(g, i, sp, save != 0);
+  phase<PH, T>(g, global_state(g), i, sp, save != 0);
 }
 
 template <typename T>
@@ -376,90 +392,106 @@ hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& s
 // barrier is the workgroup barrier, so no grid-wide synchronisation exists.
 // order[] lists graphs largest first (the hardware hands out workgroups in
 // index order, which makes this a longest-first greedy schedule).
+//
+// A graph is updated by one workgroup only, so the part of its state that
+// fits the launch's LDS stays there for all k sweeps (loaded once, written
+// back once) and every read of it, the neighbour gathers included, is served
+// on chip.  By what a 16-byte slot saves per sweep (p, q, t, s are read by
+// their owner and gathered by neighbours in two phases each, lambda and z
+// only by their owner), graphs take the largest of
+//   tier 3  p, q, t, s, lambda, z   6 slots per vertex
+//   tier 2  p, q, t, s              4
+//   tier 1  p, q                    2
+//   tier 0  none
+// whose n x slots x slot size fits the LDS bytes of the launch.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void k_graph_sweeps(DevGraph<T> g, const int32_t* __restrict__ voff,
-                               const int32_t* __restrict__ order, int k, SweepParams sp) {
-  const int gr = order[blockIdx.x];
-  const int v0 = voff[gr], v1 = voff[gr + 1];
-  if (sp.active && !sp.active[gr]) return;
-  if (sp.beta_g) sp.beta = sp.beta_g[gr];
-  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<0, T>(g, i, sp, false);
-  __syncthreads();
-  for (int it = 0; it < k; ++it) {
-    const bool save = it == k - 1;
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<1, T>(g, i, sp, save);
-    __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<2, T>(g, i, sp, save);
-    __syncthreads();
-    if (save) {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<3, T>(g, i, sp, true);
-    } else {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_mem<4, T>(g, i, sp, false);
+template <int kTier, typename T>
+__device__ __forceinline__ void graph_sweeps(const DevGraph<T>& g, int v0, int v1, int k,
+                                             const SweepParams& sp, unsigned char* lds) {
+  const int n = v1 - v0;
+  State<T> st = global_state(g);
+  Q4<T>* lq = reinterpret_cast<Q4<T>*>(lds);
+  P4<T>* lv = reinterpret_cast<P4<T>*>(lds);
+  if (kTier >= 1) {
+    st.p_ = lq;
+    st.q_ = lq + n;
+    st.pb = st.qb = v0;
+  }
+  if (kTier >= 2) {
+    st.t_ = lv + 2 * n;
+    st.s_ = lv + 3 * n;
+    st.tb = st.sb = v0;
+  }
+  if (kTier >= 3) {
+    st.lam_ = lq + 4 * n;
+    st.z_ = lv + 5 * n;
+    st.lb = st.zb = v0;
+  }
+  if (kTier >= 1) {
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
+      st.p(i) = g.p[i];
+      st.q(i) = g.q[i];
+      if (kTier >= 2) {
+        st.t(i) = g.t[i];
+        st.s(i) = g.s[i];
+      }
+      if (kTier >= 3) {
+        st.lam(i) = g.lam[i];
+        st.z(i) = g.z[i];
+      }
     }
     __syncthreads();
   }
-}
-
-// The per-graph schedule with each vertex's lambda and z held in LDS for the
-// whole launch (loaded once, written back once): only the owning thread
-// ever touches them, so LDS removes their per-sweep memory traffic.
-// Dynamic LDS: max_n slots of lambda (Q4) and z (P4).
-template <int PH, typename T>
-__device__ __forceinline__ void phase_lds(const DevGraph<T>& g, int i, const SweepParams& sp,
-                                          bool save, Q4<T>& lam, P4<T>& zs) {
-  if (PH == 0) vertex_P(g, i, sp, lam);
-  if (PH == 1) vertex_Q(g, i, sp, save, lam, g.cQ[i]);
-  if (PH == 2) vertex_T(g, i, sp, save, v3(zs), g.cT[i]);
-  if (PH == 3 || PH == 4) {
-    V3<T> z = v3(zs);
-    if (PH == 3) vertex_S(g, i, sp, save, z, g.cS[i]);
-    if (PH == 4) vertex_SP(g, i, sp, z, g.cS[i], lam);
-    zs = pad3(z);
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<0, T>(g, st, i, sp, false);
+  __syncthreads();
+  for (int it = 0; it < k; ++it) {
+    const bool save = it == k - 1;
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<1, T>(g, st, i, sp, save);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<2, T>(g, st, i, sp, save);
+    __syncthreads();
+    if (save) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<3, T>(g, st, i, sp, true);
+    } else {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<4, T>(g, st, i, sp, false);
+    }
+    __syncthreads();
+  }
+  if (kTier >= 1) {
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
+      g.p[i] = st.p(i);
+      g.q[i] = st.q(i);
+      if (kTier >= 2) {
+        g.t[i] = st.t(i);
+        g.s[i] = st.s(i);
+      }
+      if (kTier >= 3) {
+        g.lam[i] = st.lam(i);
+        g.z[i] = st.z(i);
+      }
+    }
   }
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_graph_sweeps_lds(DevGraph<T> g,
-                                                           const int32_t* __restrict__ voff,
-                                                           const int32_t* __restrict__ order,
-                                                           int k, SweepParams sp, int max_n) {
+__global__ void __launch_bounds__(1024) k_graph_sweeps(DevGraph<T> g,
+                                                       const int32_t* __restrict__ voff,
+                                                       const int32_t* __restrict__ order, int k,
+                                                       SweepParams sp, int lds_bytes) {
   extern __shared__ unsigned char lds_raw[];
-  Q4<T>* lam = reinterpret_cast<Q4<T>*>(lds_raw);
-  P4<T>* zz = reinterpret_cast<P4<T>*>(lds_raw + sizeof(Q4<T>) * size_t(max_n));
   const int gr = order[blockIdx.x];
   const int v0 = voff[gr], v1 = voff[gr + 1];
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
-  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
-    lam[i - v0] = g.lam[i];
-    zz[i - v0] = g.z[i];
-  }
-  // each slot is read and written only by the thread that loaded it
-  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
-    phase_lds<0, T>(g, i, sp, false, lam[i - v0], zz[i - v0]);
-  __syncthreads();
-  for (int it = 0; it < k; ++it) {
-    const bool save = it == k - 1;
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
-      phase_lds<1, T>(g, i, sp, save, lam[i - v0], zz[i - v0]);
-    __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
-      phase_lds<2, T>(g, i, sp, save, lam[i - v0], zz[i - v0]);
-    __syncthreads();
-    if (save) {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
-        phase_lds<3, T>(g, i, sp, true, lam[i - v0], zz[i - v0]);
-    } else {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
-        phase_lds<4, T>(g, i, sp, false, lam[i - v0], zz[i - v0]);
-    }
-    __syncthreads();
-  }
-  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
-    g.lam[i] = lam[i - v0];
-    g.z[i] = zz[i - v0];
-  }
+  const size_t per = size_t(v1 - v0) * sizeof(Q4<T>);
+  if (6 * per <= size_t(lds_bytes))
+    graph_sweeps<3, T>(g, v0, v1, k, sp, lds_raw);
+  else if (4 * per <= size_t(lds_bytes))
+    graph_sweeps<2, T>(g, v0, v1, k, sp, lds_raw);
+  else if (2 * per <= size_t(lds_bytes))
+    graph_sweeps<1, T>(g, v0, v1, k, sp, lds_raw);
+  else
+    graph_sweeps<0, T>(g, v0, v1, k, sp, lds_raw);
 }
 
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -467,19 +499,21 @@ constexpr size_t kLdsBytes = 160 * 1024;
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
                                int G, int k, const SweepParams& sp, int block, int max_n,
-                               int regs, hipStream_t st) {
+                               int lds, hipStream_t st) {
+  static_assert(sizeof(Q4<T>) == sizeof(P4<T>), "one slot size for every state array");
   if (G <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
-  const size_t lds = (sizeof(Q4<T>) + sizeof(P4<T>)) * size_t(max_n);
-  if (regs && lds <= kLdsBytes &&
-      hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_lds<T>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)) == hipSuccess) {
-    hipLaunchKernelGGL((k_graph_sweeps_lds<T>), dim3(G), dim3(block), lds, st, g, voff, order, k,
-                       sp, max_n);
-    return hipGetLastError();
+  // enough for the largest graph's tier 3, within the 160 KiB of a CU
+  size_t bytes = lds ? std::min(kLdsBytes, 6 * sizeof(Q4<T>) * size_t(max_n)) : 0;
+  if (bytes < 2 * sizeof(Q4<T>)) bytes = 0;
+  if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   int(bytes)) != hipSuccess) {
+    (void)hipGetLastError();  // clear a refused request; run without LDS residency
+    bytes = 0;
   }
-  (void)hipGetLastError();  // clear a refused attribute request; use the plain kernel
-  hipLaunchKernelGGL((k_graph_sweeps<T>), dim3(G), dim3(block), 0, st, g, voff, order, k, sp);
+  hipLaunchKernelGGL((k_graph_sweeps<T>), dim3(G), dim3(block), bytes, st, g, voff, order, k, sp,
+                     int(bytes));
   return hipGetLastError();
 }
 
