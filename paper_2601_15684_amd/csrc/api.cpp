@@ -204,9 +204,9 @@ DevChordal<T> viewc(const pgo_graph* g) {
 }
 
 // Whether the per-graph kernel can keep graphs' state in LDS for a launch
-// (the quaternion model; each graph takes the largest residency tier that
-// fits, see launch_graph_sweeps).
-bool lds_fits(const pgo_graph* g) { return !g->chordal && !g->aniso; }
+// (quaternion and chordal models; each graph keeps what fits, see
+// launch_graph_sweeps and launch_graph_sweeps_c).
+bool lds_fits(const pgo_graph* g) { return !g->aniso; }
 
 template <typename T>
 DevAniso<T> viewa(const pgo_graph* g) {
@@ -616,7 +616,8 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
   const DevAniso<T> da = viewa<T>(g);
   if (sched == PGO_SCHED_GRAPH) {
     if (g->chordal)
-      HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->stream));
+      HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->max_n,
+                                      g->graph_lds, g->stream));
     else if (g->aniso)
       HIPCHK(launch_graph_sweeps_a<T>(da, g->voff32, g->order, g->G, k, sp, block, g->stream));
     else

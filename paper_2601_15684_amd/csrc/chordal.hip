@@ -71,6 +71,31 @@ __device__ __forceinline__ A l1_9(const A m[9]) {
   return s;
 }
 
+// Where the state of the vertices being updated lives: each array either
+// in global memory (base 0) or, in the per-graph kernel, in LDS for the
+// graph's vertices v0.. (base v0); element j of an array is x[j - xb].
+template <typename T>
+struct StateC {
+  R3<T>* P_;
+  R3<T>* Q_;
+  R3<T>* L_;
+  P4<T>* t_;
+  P4<T>* s_;
+  P4<T>* z_;
+  int Pb, Qb, Lb, tb, sb, zb;
+  __device__ __forceinline__ R3<T>& P(int j) const { return P_[j - Pb]; }
+  __device__ __forceinline__ R3<T>& Q(int j) const { return Q_[j - Qb]; }
+  __device__ __forceinline__ R3<T>& L(int j) const { return L_[j - Lb]; }
+  __device__ __forceinline__ P4<T>& t(int j) const { return t_[j - tb]; }
+  __device__ __forceinline__ P4<T>& s(int j) const { return s_[j - sb]; }
+  __device__ __forceinline__ P4<T>& z(int j) const { return z_[j - zb]; }
+};
+
+template <typename T>
+__device__ __forceinline__ StateC<T> global_state(const DevChordal<T>& g) {
+  return {g.P, g.Q, g.L, g.t, g.s, g.z, 0, 0, 0, 0, 0, 0};
+}
+
 // Out-edge part of M_i.  Each term (t_j - s_i) u_e^T (u_e = tau t~_e) is
 // linear in s_i, so the sum over the out-edges is
 //   sum (t_j - t_i) u_e^T + (t_i - s_i) (sum u_e)^T,
@@ -110,7 +135,8 @@ __device__ __forceinline__ void m_out_add(MOut<A>& mo, const A ti[3], const P4<T
 // out-edge part is taken from pre when the caller gathered it already.
 // mag collects the L1 size of every term (FP32 conditioning check only).
 template <typename A, typename T, bool kMag>
-__device__ void p_matrix(const DevChordal<T>& g, int i, const SweepParams& sp, const R3<T>& Qi_,
+__device__ void p_matrix(const DevChordal<T>& g, const StateC<T>& st, int i, const SweepParams& sp,
+                         const R3<T>& Qi_,
                          const P4<T>& ti_, const P4<T>& si_, const R3<T>& Pi_, const R3<T>& Li_,
                          A M[9], A& mag, const MOut<A>* pre = nullptr) {
   const A ti[3] = {A(ti_.x), A(ti_.y), A(ti_.z)};
@@ -123,7 +149,7 @@ __device__ void p_matrix(const DevChordal<T>& g, int i, const SweepParams& sp, c
       P4<T> tj, u;
     };
     edge_loop(
-        g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.t[g.o_nbr[e]], g.o_tt[e]}; },
+        g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{st.t(g.o_nbr[e]), g.o_tt[e]}; },
         [&](const OutE& x) { m_out_add<A, kMag>(mo, ti, x.tj, x.u); });
   }
   const A ds[3] = {ti[0] - A(si_.x), ti[1] - A(si_.y), ti[2] - A(si_.z)};  // t_i - s_i
@@ -139,7 +165,7 @@ __device__ void p_matrix(const DevChordal<T>& g, int i, const SweepParams& sp, c
     R3<T> Ql, W;
   };
   edge_loop<1>(  // two 3x3 pairs in flight would spill registers
-      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{g.Q[g.i_nbr[e]], g.i_R[e]}; },
+      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{st.Q(g.i_nbr[e]), g.i_R[e]}; },
       [&](const InE& x) {
         A Ql[9], W[9];
         ld9<A>(x.Ql, Ql);
@@ -175,26 +201,27 @@ __device__ __forceinline__ A polar_gap(const A M[9], const A sig[3]) {
 // P update of vertex i from its own values (passed in, as the fused S+P
 // phase has them in registers).  P_i is kept when M_i = 0.
 template <typename T>
-__device__ void vertex_P_own(const DevChordal<T>& g, int i, const SweepParams& sp,
-                             const R3<T>& Qi, const P4<T>& ti, const P4<T>& si, const R3<T>& Pi,
-                             const R3<T>& Li, const MOut<T>* pre = nullptr) {
+__device__ void vertex_P_own(const DevChordal<T>& g, const StateC<T>& st, int i,
+                             const SweepParams& sp, const R3<T>& Qi, const P4<T>& ti,
+                             const P4<T>& si, const R3<T>& Pi, const R3<T>& Li,
+                             const MOut<T>* pre = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   T M[9], R[9], sig[3], mag = T(0);
-  p_matrix<T, T, kF32>(g, i, sp, Qi, ti, si, Pi, Li, M, mag, pre);
+  p_matrix<T, T, kF32>(g, st, i, sp, Qi, ti, si, Pi, Li, M, mag, pre);
   polar3<T>(M, R, sig);
   if (kF32 && !(polar_gap<T>(M, sig) >= T(1e-2) * mag)) {
     double Md[9], Rd[9], sd[3], dm = 0.0;
-    p_matrix<double, T, false>(g, i, sp, Qi, ti, si, Pi, Li, Md, dm);
+    p_matrix<double, T, false>(g, st, i, sp, Qi, ti, si, Pi, Li, Md, dm);
     polar3<double>(Md, Rd, sd);
-    if (sd[0] > 0.0 || sd[1] > 0.0 || sd[2] > 0.0) g.P[i] = st9<T, double>(Rd);
+    if (sd[0] > 0.0 || sd[1] > 0.0 || sd[2] > 0.0) st.P(i) = st9<T, double>(Rd);
     return;
   }
-  if (sig[0] > T(0) || sig[1] > T(0) || sig[2] > T(0)) g.P[i] = st9<T, T>(R);
+  if (sig[0] > T(0) || sig[1] > T(0) || sig[2] > T(0)) st.P(i) = st9<T, T>(R);
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, int i, const SweepParams& sp,
-                                         bool save, R3<T>& lam, T cQ) {
+__device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, const StateC<T>& st, int i,
+                                         const SweepParams& sp, bool save) {
   T acc[9];
 #pragma unroll
   for (int k = 0; k < 9; ++k) acc[k] = T(0);
@@ -202,7 +229,7 @@ __device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, int i, const Sw
     R3<T> Pj, W;
   };
   edge_loop<1>(
-      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.P[g.o_nbr[e]], g.o_R[e]}; },
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{st.P(g.o_nbr[e]), g.o_R[e]}; },
       [&](const OutE& x) {
         T Pj[9], W[9];
         ld9<T>(x.Pj, Pj);
@@ -215,12 +242,12 @@ __device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, int i, const Sw
                               Pj[3 * r + 2] * W[3 * c + 2];
       });
   T Pi[9], Qi[9], Li[9], Qn[9], Ln[9];
-  const R3<T> Qold = g.Q[i];
-  ld9<T>(g.P[i], Pi);
+  const R3<T> Qold = st.Q(i), lam = st.L(i);
+  ld9<T>(st.P(i), Pi);
   ld9<T>(Qold, Qi);
   ld9<T>(lam, Li);
   const T b = T(sp.beta), h = T(sp.h2);
-  const T a = cQ + b + h;
+  const T a = g.cQ[i] + b + h;
   const T gb = T(sp.gamma * sp.beta);
 #pragma unroll
   for (int k = 0; k < 9; ++k) {
@@ -231,8 +258,8 @@ __device__ __forceinline__ void vertex_Q(const DevChordal<T>& g, int i, const Sw
     g.Q_prev[i] = Qold;
     g.L_prev[i] = lam;
   }
-  g.Q[i] = st9<T, T>(Qn);
-  lam = st9<T, T>(Ln);
+  st.Q(i) = st9<T, T>(Qn);
+  st.L(i) = st9<T, T>(Ln);
 }
 
 template <typename T>
@@ -243,8 +270,8 @@ __device__ __forceinline__ V3<T> mat_vec(const R3<T>& m, const P4<T>& v) {
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_T(const DevChordal<T>& g, int i, const SweepParams& sp,
-                                         bool save, const V3<T>& zi, T cT) {
+__device__ __forceinline__ void vertex_T(const DevChordal<T>& g, const StateC<T>& st, int i,
+                                         const SweepParams& sp, bool save) {
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
     P4<T> u, sl;
@@ -254,7 +281,7 @@ __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, int i, const Sw
       g.i_ptr[i], g.i_ptr[i + 1],
       [&](int e) {
         const int l = g.i_nbr[e];
-        return InE{g.i_tt[e], g.s[l], g.P[l]};
+        return InE{g.i_tt[e], st.s(l), st.P(l)};
       },
       [&](const InE& x) {
         const V3<T> c = mat_vec(x.Pl, x.u);  // P_l (tau t~)
@@ -262,30 +289,32 @@ __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, int i, const Sw
         acc.y += x.u.u * x.sl.y + c.y;
         acc.z += x.u.u * x.sl.z + c.z;
       });
-  const P4<T> ti = g.t[i], si = g.s[i];
+  const P4<T> ti = st.t(i), si = st.s(i);
+  const V3<T> zi = v3(st.z(i));
   const T b = T(sp.beta), h = T(sp.h3);
-  const T a = cT + b + h;
+  const T a = g.cT[i] + b + h;
   if (save) g.t_prev[i] = ti;
-  g.t[i] = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
-                 (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
-                 (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
+  st.t(i) = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+                  (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
+                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const SweepParams& sp,
-                                         bool save, V3<T>& z, T cS, R3<T>* P_out = nullptr,
-                                         R3<T>* Q_out = nullptr, P4<T>* t_out = nullptr,
-                                         P4<T>* s_out = nullptr, MOut<T>* mo = nullptr) {
+__device__ __forceinline__ void vertex_S(const DevChordal<T>& g, const StateC<T>& st, int i,
+                                         const SweepParams& sp, bool save,
+                                         R3<T>* P_out = nullptr, R3<T>* Q_out = nullptr,
+                                         P4<T>* t_out = nullptr, P4<T>* s_out = nullptr,
+                                         MOut<T>* mo = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
-  const R3<T> Pi = g.P[i];
-  const P4<T> ti = g.t[i], si = g.s[i];
+  const R3<T> Pi = st.P(i);
+  const P4<T> ti = st.t(i), si = st.s(i);
   const T tiv[3] = {ti.x, ti.y, ti.z};
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
     P4<T> u, tj;
   };
   edge_loop(
-      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]]}; },
+      g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e])}; },
       [&](const OutE& x) {
         const V3<T> c = mat_vec(Pi, x.u);  // P_i (tau t~)
         acc.x += x.u.u * x.tj.x - c.x;
@@ -293,9 +322,9 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const Sw
         acc.z += x.u.u * x.tj.z - c.z;
         if (mo) m_out_add<T, kF32>(*mo, tiv, x.tj, x.u);  // the next P's out-edge sum
       });
-  const V3<T> zi = z;
+  const V3<T> zi = v3(st.z(i));
   const T b = T(sp.beta), h = T(sp.h4);
-  const T a = cS + b + h;
+  const T a = g.cS[i] + b + h;
   const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
                     (T(2) * acc.y + b * ti.y - zi.y + h * si.y) / a,
                     (T(2) * acc.z + b * ti.z - zi.z + h * si.z) / a};
@@ -304,40 +333,31 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, int i, const Sw
     g.s_prev[i] = si;
     g.z_prev[i] = pad3(zi);
   }
-  g.s[i] = pad3(sn);
-  z = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  st.s(i) = pad3(sn);
+  st.z(i) = pad3(V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
+                       zi.z - gb * (ti.z - sn.z)});
   if (P_out) {
     *P_out = Pi;
-    *Q_out = g.Q[i];
+    *Q_out = st.Q(i);
     *t_out = ti;
     *s_out = pad3(sn);
   }
 }
 
 template <int PH, typename T>
-__device__ __forceinline__ void phase_c(const DevChordal<T>& g, int i, const SweepParams& sp,
-                                        bool save) {
-  if (PH == 0) vertex_P_own(g, i, sp, g.Q[i], g.t[i], g.s[i], g.P[i], g.L[i]);
-  if (PH == 1) {
-    R3<T> l = g.L[i];
-    vertex_Q(g, i, sp, save, l, g.cQ[i]);
-    g.L[i] = l;
-  }
-  if (PH == 2) vertex_T(g, i, sp, save, v3(g.z[i]), g.cT[i]);
-  if (PH == 3) {
-    V3<T> z = v3(g.z[i]);
-    vertex_S(g, i, sp, save, z, g.cS[i]);
-    g.z[i] = pad3(z);
-  }
+__device__ __forceinline__ void phase_c(const DevChordal<T>& g, const StateC<T>& st, int i,
+                                        const SweepParams& sp, bool save) {
+  if (PH == 0) vertex_P_own(g, st, i, sp, st.Q(i), st.t(i), st.s(i), st.P(i), st.L(i));
+  if (PH == 1) vertex_Q(g, st, i, sp, save);
+  if (PH == 2) vertex_T(g, st, i, sp, save);
+  if (PH == 3) vertex_S(g, st, i, sp, save);
   if (PH == 4) {  // S of this sweep + P of the next
-    V3<T> z = v3(g.z[i]);
     R3<T> Pi, Qi;
     P4<T> ti, si;
     MOut<T> mo;
     m_out_zero(mo);
-    vertex_S(g, i, sp, false, z, g.cS[i], &Pi, &Qi, &ti, &si, &mo);
-    g.z[i] = pad3(z);
-    vertex_P_own(g, i, sp, Qi, ti, si, Pi, g.L[i], &mo);
+    vertex_S(g, st, i, sp, false, &Pi, &Qi, &ti, &si, &mo);
+    vertex_P_own(g, st, i, sp, Qi, ti, si, Pi, st.L(i), &mo);
   }
 }
 
@@ -358,30 +378,94 @@ __global__ void k_phase_c(DevChordal<T> g, SweepParams sp, int save) {
   if (i >= g.n) return;
   if (sp.active && !sp.active[g.gid[i]]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[g.gid[i]];
-  phase_c<PH, T>(g, i, sp, save != 0);
+  phase_c<PH, T>(g, global_state(g), i, sp, save != 0);
+}
+
+// One persistent workgroup per graph, as in the quaternion sweep, with the
+// part of the graph's state that fits the launch's LDS held there for all k
+// sweeps.  The arrays go to LDS in the order of what a byte saves per
+// sweep: s and P are read and written by their owner and gathered by
+// neighbours (s in T; P in Q and T), t and Q likewise with fewer reads, z and
+// Lambda only by their owner.  A graph keeps the first kArrays of
+// s, P, t, Q, z, Lambda whose slots fit.
+template <typename T>
+__device__ __forceinline__ size_t lds_prefix_c(int k) {
+  // bytes per vertex of the first k arrays of s, P, t, Q, z, Lambda
+  const size_t v = sizeof(P4<T>), r = sizeof(R3<T>);
+  const size_t c[7] = {0, v, v + r, 2 * v + r, 2 * v + 2 * r, 3 * v + 2 * r, 3 * v + 3 * r};
+  return c[k];
+}
+
+template <int kArrays, typename T>
+__device__ __forceinline__ void graph_sweeps_c(const DevChordal<T>& g, int v0, int v1, int k,
+                                               const SweepParams& sp, unsigned char* lds) {
+  const int n = v1 - v0;
+  StateC<T> st = global_state(g);
+  unsigned char* at = lds;
+  if (kArrays >= 1) st.s_ = reinterpret_cast<P4<T>*>(at), st.sb = v0, at += sizeof(P4<T>) * n;
+  if (kArrays >= 2) st.P_ = reinterpret_cast<R3<T>*>(at), st.Pb = v0, at += sizeof(R3<T>) * n;
+  if (kArrays >= 3) st.t_ = reinterpret_cast<P4<T>*>(at), st.tb = v0, at += sizeof(P4<T>) * n;
+  if (kArrays >= 4) st.Q_ = reinterpret_cast<R3<T>*>(at), st.Qb = v0, at += sizeof(R3<T>) * n;
+  if (kArrays >= 5) st.z_ = reinterpret_cast<P4<T>*>(at), st.zb = v0, at += sizeof(P4<T>) * n;
+  if (kArrays >= 6) st.L_ = reinterpret_cast<R3<T>*>(at), st.Lb = v0;
+  if (kArrays >= 1) {
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
+      st.s(i) = g.s[i];
+      if (kArrays >= 2) st.P(i) = g.P[i];
+      if (kArrays >= 3) st.t(i) = g.t[i];
+      if (kArrays >= 4) st.Q(i) = g.Q[i];
+      if (kArrays >= 5) st.z(i) = g.z[i];
+      if (kArrays >= 6) st.L(i) = g.L[i];
+    }
+    __syncthreads();
+  }
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<0, T>(g, st, i, sp, false);
+  __syncthreads();
+  for (int it = 0; it < k; ++it) {
+    const bool save = it == k - 1;
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<1, T>(g, st, i, sp, save);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<2, T>(g, st, i, sp, save);
+    __syncthreads();
+    if (save) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<3, T>(g, st, i, sp, true);
+    } else {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<4, T>(g, st, i, sp, false);
+    }
+    __syncthreads();
+  }
+  if (kArrays >= 1) {  // each thread writes back the slots only it wrote
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
+      g.s[i] = st.s(i);
+      if (kArrays >= 2) g.P[i] = st.P(i);
+      if (kArrays >= 3) g.t[i] = st.t(i);
+      if (kArrays >= 4) g.Q[i] = st.Q(i);
+      if (kArrays >= 5) g.z[i] = st.z(i);
+      if (kArrays >= 6) g.L[i] = st.L(i);
+    }
+  }
 }
 
 template <typename T>
 __global__ void k_graph_sweeps_c(DevChordal<T> g, const int32_t* __restrict__ voff,
-                                 const int32_t* __restrict__ order, int k, SweepParams sp) {
+                                 const int32_t* __restrict__ order, int k, SweepParams sp,
+                                 int lds_bytes) {
+  extern __shared__ unsigned char lds_raw[];
   const int gr = order[blockIdx.x];
   const int v0 = voff[gr], v1 = voff[gr + 1];
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
-  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<0, T>(g, i, sp, false);
-  __syncthreads();
-  for (int it = 0; it < k; ++it) {
-    const bool save = it == k - 1;
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<1, T>(g, i, sp, save);
-    __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<2, T>(g, i, sp, save);
-    __syncthreads();
-    if (save) {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<3, T>(g, i, sp, true);
-    } else {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_c<4, T>(g, i, sp, false);
-    }
-    __syncthreads();
+  const size_t n = size_t(v1 - v0);
+  int arrays = 0;
+  while (arrays < 6 && lds_prefix_c<T>(arrays + 1) * n <= size_t(lds_bytes)) ++arrays;
+  switch (arrays) {
+    case 6: graph_sweeps_c<6, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 5: graph_sweeps_c<5, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 4: graph_sweeps_c<4, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 3: graph_sweeps_c<3, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 2: graph_sweeps_c<2, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 1: graph_sweeps_c<1, T>(g, v0, v1, k, sp, lds_raw); break;
+    default: graph_sweeps_c<0, T>(g, v0, v1, k, sp, lds_raw); break;
   }
 }
 
@@ -542,10 +626,22 @@ hipError_t launch_phase_sweeps_c(const DevChordal<T>& g, int k, const SweepParam
 
 template <typename T>
 hipError_t launch_graph_sweeps_c(const DevChordal<T>& g, const int32_t* voff, const int32_t* order,
-                                 int G, int k, const SweepParams& sp, int block, hipStream_t st) {
+                                 int G, int k, const SweepParams& sp, int block, int max_n, int lds,
+                                 hipStream_t st) {
   if (G <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_graph_sweeps_c<T>), dim3(G), dim3(block), 0, st, g, voff, order, k, sp);
+  // enough for all six arrays of the largest graph, within the 160 KiB of a CU
+  constexpr size_t kLds = 160 * 1024;
+  const size_t all = 3 * (sizeof(P4<T>) + sizeof(R3<T>));
+  size_t bytes = lds ? std::min(kLds, all * size_t(max_n)) : 0;
+  if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_c<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   int(bytes)) != hipSuccess) {
+    (void)hipGetLastError();  // clear a refused request; run without LDS residency
+    bytes = 0;
+  }
+  hipLaunchKernelGGL((k_graph_sweeps_c<T>), dim3(G), dim3(block), bytes, st, g, voff, order, k,
+                     sp, int(bytes));
   return hipGetLastError();
 }
 
@@ -603,7 +699,7 @@ hipError_t launch_poses_c(const DevChordal<T>& g, double* R, double* t, hipStrea
                                                int, hipStream_t);                                \
   template hipError_t launch_graph_sweeps_c<T>(const DevChordal<T>&, const int32_t*,            \
                                                const int32_t*, int, int, const SweepParams&,     \
-                                               int, hipStream_t);                                \
+                                               int, int, int, hipStream_t);                      \
   template hipError_t launch_fill_edges_c<T>(const int32_t*, const int32_t*, const double*,     \
                                              const double*, const double*, const double*,       \
                                              int64_t, int32_t*, P4<T>*, R3<T>*, hipStream_t);    \

@@ -171,8 +171,11 @@ template <typename T>
 hipError_t launch_phase_sweeps_c(const DevChordal<T>& g, int k, const SweepParams& sp, int block,
                                  hipStream_t st);
 template <typename T>
+// lds != 0: each graph keeps the part of its state that fits in LDS there
+// for the whole launch (s, P, t, Q, z, Lambda in that order, by graph size).
 hipError_t launch_graph_sweeps_c(const DevChordal<T>& g, const int32_t* voff, const int32_t* order,
-                                 int G, int k, const SweepParams& sp, int block, hipStream_t st);
+                                 int G, int k, const SweepParams& sp, int block, int max_n, int lds,
+                                 hipStream_t st);
 // projection of 3x3 matrices onto SO(3) with the validity rule of
 // launch_rot_to_quat (det > 0 and ||A^T A - I||_F <= 1e-2, else bad[i] = 1)
 hipError_t launch_project_rot(const double* R, int64_t count, double* out, uint8_t* bad,

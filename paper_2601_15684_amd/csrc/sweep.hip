@@ -396,49 +396,33 @@ hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& s
 // A graph is updated by one workgroup only, so the part of its state that
 // fits the launch's LDS stays there for all k sweeps (loaded once, written
 // back once) and every read of it, the neighbour gathers included, is served
-// on chip.  By what a 16-byte slot saves per sweep (p, q, t, s are read by
-// their owner and gathered by neighbours in two phases each, lambda and z
-// only by their owner), graphs take the largest of
-//   tier 3  p, q, t, s, lambda, z   6 slots per vertex
-//   tier 2  p, q, t, s              4
-//   tier 1  p, q                    2
-//   tier 0  none
-// whose n x slots x slot size fits the LDS bytes of the launch.
+// on chip.  The arrays go to LDS in the order of what a slot saves per
+// sweep: p, q and t are read by their owner and gathered by neighbours in
+// two phases each, s in one, lambda and z only by their owner.  A graph of
+// n vertices keeps the first kSlots of p, q, t, s, lambda, z there, kSlots
+// the most whose n x kSlots slots fit the launch's LDS.
 // ---------------------------------------------------------------------------
-template <int kTier, typename T>
+template <int kSlots, typename T>
 __device__ __forceinline__ void graph_sweeps(const DevGraph<T>& g, int v0, int v1, int k,
                                              const SweepParams& sp, unsigned char* lds) {
   const int n = v1 - v0;
   State<T> st = global_state(g);
   Q4<T>* lq = reinterpret_cast<Q4<T>*>(lds);
   P4<T>* lv = reinterpret_cast<P4<T>*>(lds);
-  if (kTier >= 1) {
-    st.p_ = lq;
-    st.q_ = lq + n;
-    st.pb = st.qb = v0;
-  }
-  if (kTier >= 2) {
-    st.t_ = lv + 2 * n;
-    st.s_ = lv + 3 * n;
-    st.tb = st.sb = v0;
-  }
-  if (kTier >= 3) {
-    st.lam_ = lq + 4 * n;
-    st.z_ = lv + 5 * n;
-    st.lb = st.zb = v0;
-  }
-  if (kTier >= 1) {
+  if (kSlots >= 1) st.p_ = lq, st.pb = v0;
+  if (kSlots >= 2) st.q_ = lq + n, st.qb = v0;
+  if (kSlots >= 3) st.t_ = lv + 2 * n, st.tb = v0;
+  if (kSlots >= 4) st.s_ = lv + 3 * n, st.sb = v0;
+  if (kSlots >= 5) st.lam_ = lq + 4 * n, st.lb = v0;
+  if (kSlots >= 6) st.z_ = lv + 5 * n, st.zb = v0;
+  if (kSlots >= 1) {
     for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
       st.p(i) = g.p[i];
-      st.q(i) = g.q[i];
-      if (kTier >= 2) {
-        st.t(i) = g.t[i];
-        st.s(i) = g.s[i];
-      }
-      if (kTier >= 3) {
-        st.lam(i) = g.lam[i];
-        st.z(i) = g.z[i];
-      }
+      if (kSlots >= 2) st.q(i) = g.q[i];
+      if (kSlots >= 3) st.t(i) = g.t[i];
+      if (kSlots >= 4) st.s(i) = g.s[i];
+      if (kSlots >= 5) st.lam(i) = g.lam[i];
+      if (kSlots >= 6) st.z(i) = g.z[i];
     }
     __syncthreads();
   }
@@ -457,18 +441,14 @@ __device__ __forceinline__ void graph_sweeps(const DevGraph<T>& g, int v0, int v
     }
     __syncthreads();
   }
-  if (kTier >= 1) {
+  if (kSlots >= 1) {  // each thread writes back the slots only it wrote
     for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
       g.p[i] = st.p(i);
-      g.q[i] = st.q(i);
-      if (kTier >= 2) {
-        g.t[i] = st.t(i);
-        g.s[i] = st.s(i);
-      }
-      if (kTier >= 3) {
-        g.lam[i] = st.lam(i);
-        g.z[i] = st.z(i);
-      }
+      if (kSlots >= 2) g.q[i] = st.q(i);
+      if (kSlots >= 3) g.t[i] = st.t(i);
+      if (kSlots >= 4) g.s[i] = st.s(i);
+      if (kSlots >= 5) g.lam[i] = st.lam(i);
+      if (kSlots >= 6) g.z[i] = st.z(i);
     }
   }
 }
@@ -484,14 +464,16 @@ __global__ void __launch_bounds__(1024) k_graph_sweeps(DevGraph<T> g,
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
   const size_t per = size_t(v1 - v0) * sizeof(Q4<T>);
-  if (6 * per <= size_t(lds_bytes))
-    graph_sweeps<3, T>(g, v0, v1, k, sp, lds_raw);
-  else if (4 * per <= size_t(lds_bytes))
-    graph_sweeps<2, T>(g, v0, v1, k, sp, lds_raw);
-  else if (2 * per <= size_t(lds_bytes))
-    graph_sweeps<1, T>(g, v0, v1, k, sp, lds_raw);
-  else
-    graph_sweeps<0, T>(g, v0, v1, k, sp, lds_raw);
+  const int slots = int(std::min<size_t>(6, size_t(lds_bytes) / per));
+  switch (slots) {
+    case 6: graph_sweeps<6, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 5: graph_sweeps<5, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 4: graph_sweeps<4, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 3: graph_sweeps<3, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 2: graph_sweeps<2, T>(g, v0, v1, k, sp, lds_raw); break;
+    case 1: graph_sweeps<1, T>(g, v0, v1, k, sp, lds_raw); break;
+    default: graph_sweeps<0, T>(g, v0, v1, k, sp, lds_raw); break;
+  }
 }
 
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -503,9 +485,8 @@ hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const 
   static_assert(sizeof(Q4<T>) == sizeof(P4<T>), "one slot size for every state array");
   if (G <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
-  // enough for the largest graph's tier 3, within the 160 KiB of a CU
+  // enough for all six arrays of the largest graph, within the 160 KiB of a CU
   size_t bytes = lds ? std::min(kLdsBytes, 6 * sizeof(Q4<T>) * size_t(max_n)) : 0;
-  if (bytes < 2 * sizeof(Q4<T>)) bytes = 0;
   if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    int(bytes)) != hipSuccess) {
