@@ -205,7 +205,9 @@ DevChordal<T> viewc(const pgo_graph* g) {
 
 // Whether the per-graph kernel can keep graphs' state in LDS for a launch
 // (quaternion and chordal models; each graph keeps what fits, see
-// launch_graph_sweeps and launch_graph_sweeps_c).
+// launch_graph_sweeps and launch_graph_sweeps_c).  The information model's
+// P update leaves registers for two 256-thread workgroups per CU, and
+// sharing the LDS between them measured slower than none.
 bool lds_fits(const pgo_graph* g) { return !g->aniso; }
 
 template <typename T>

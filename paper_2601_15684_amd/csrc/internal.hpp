@@ -50,6 +50,79 @@ struct DevGraph {
   P4<T>* z_prev;
 };
 
+// Where the state of the vertices being updated lives during a sweep: each
+// array either in global memory (base 0) or, in a per-graph kernel, in LDS
+// for the graph's vertices v0.. (base v0); element j of an array is
+// x[j - xb].
+template <typename T>
+struct State {
+  Q4<T>* p_;
+  Q4<T>* q_;
+  P4<T>* t_;
+  P4<T>* s_;
+  Q4<T>* lam_;
+  P4<T>* z_;
+  int pb, qb, tb, sb, lb, zb;
+  __device__ __forceinline__ Q4<T>& p(int j) const { return p_[j - pb]; }
+  __device__ __forceinline__ Q4<T>& q(int j) const { return q_[j - qb]; }
+  __device__ __forceinline__ P4<T>& t(int j) const { return t_[j - tb]; }
+  __device__ __forceinline__ P4<T>& s(int j) const { return s_[j - sb]; }
+  __device__ __forceinline__ Q4<T>& lam(int j) const { return lam_[j - lb]; }
+  __device__ __forceinline__ P4<T>& z(int j) const { return z_[j - zb]; }
+};
+
+template <typename T>
+__device__ __forceinline__ State<T> global_state(const DevGraph<T>& g) {
+  return {g.p, g.q, g.t, g.s, g.lam, g.z, 0, 0, 0, 0, 0, 0};
+}
+
+// Places the first k of p, q, t, s, lambda, z of the graph's vertices
+// [v0, v1) in LDS (k slots of sizeof(Q4<T>) per vertex from lds), loads
+// them, and returns the view; the caller runs its sweeps and hands the view
+// to state_store.  Every vertex's slots are written only by the thread that
+// owns the vertex, which also loads and stores them.
+template <int kSlots, typename T>
+__device__ __forceinline__ State<T> state_load(const DevGraph<T>& g, int v0, int v1,
+                                               unsigned char* lds) {
+  const int n = v1 - v0;
+  State<T> st = global_state(g);
+  Q4<T>* lq = reinterpret_cast<Q4<T>*>(lds);
+  P4<T>* lv = reinterpret_cast<P4<T>*>(lds);
+  if (kSlots >= 1) st.p_ = lq, st.pb = v0;
+  if (kSlots >= 2) st.q_ = lq + n, st.qb = v0;
+  if (kSlots >= 3) st.t_ = lv + 2 * n, st.tb = v0;
+  if (kSlots >= 4) st.s_ = lv + 3 * n, st.sb = v0;
+  if (kSlots >= 5) st.lam_ = lq + 4 * n, st.lb = v0;
+  if (kSlots >= 6) st.z_ = lv + 5 * n, st.zb = v0;
+  if (kSlots >= 1) {
+    for (int i = v0 + int(threadIdx.x); i < v1; i += int(blockDim.x)) {
+      st.p(i) = g.p[i];
+      if (kSlots >= 2) st.q(i) = g.q[i];
+      if (kSlots >= 3) st.t(i) = g.t[i];
+      if (kSlots >= 4) st.s(i) = g.s[i];
+      if (kSlots >= 5) st.lam(i) = g.lam[i];
+      if (kSlots >= 6) st.z(i) = g.z[i];
+    }
+    __syncthreads();
+  }
+  return st;
+}
+
+template <int kSlots, typename T>
+__device__ __forceinline__ void state_store(const DevGraph<T>& g, const State<T>& st, int v0,
+                                            int v1) {
+  if (kSlots >= 1) {
+    for (int i = v0 + int(threadIdx.x); i < v1; i += int(blockDim.x)) {
+      g.p[i] = st.p(i);
+      if (kSlots >= 2) g.q[i] = st.q(i);
+      if (kSlots >= 3) g.t[i] = st.t(i);
+      if (kSlots >= 4) g.s[i] = st.s(i);
+      if (kSlots >= 5) g.lam[i] = st.lam(i);
+      if (kSlots >= 6) g.z[i] = st.z(i);
+    }
+  }
+}
+
 struct SweepParams {
   double beta, gamma, h1, h2, h3, h4;
   const double* beta_g;   // per-graph penalties (device, G values) or nullptr

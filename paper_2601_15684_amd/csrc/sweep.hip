@@ -98,31 +98,6 @@ __device__ __forceinline__ Q4<A> p_out_finish(const POut<A>& po, const Q4<A>& qi
   return {head.w + po.x.w, head.x + po.x.x, head.y + po.x.y, head.z + po.x.z};
 }
 
-// Where the state of the vertices being updated lives: each array either
-// in global memory (base 0) or, in the per-graph kernel, in LDS for the
-// graph's vertices v0.. (base v0); element j of an array is x[j - xb].
-template <typename T>
-struct State {
-  Q4<T>* p_;
-  Q4<T>* q_;
-  P4<T>* t_;
-  P4<T>* s_;
-  Q4<T>* lam_;
-  P4<T>* z_;
-  int pb, qb, tb, sb, lb, zb;
-  __device__ __forceinline__ Q4<T>& p(int j) const { return p_[j - pb]; }
-  __device__ __forceinline__ Q4<T>& q(int j) const { return q_[j - qb]; }
-  __device__ __forceinline__ P4<T>& t(int j) const { return t_[j - tb]; }
-  __device__ __forceinline__ P4<T>& s(int j) const { return s_[j - sb]; }
-  __device__ __forceinline__ Q4<T>& lam(int j) const { return lam_[j - lb]; }
-  __device__ __forceinline__ P4<T>& z(int j) const { return z_[j - zb]; }
-};
-
-template <typename T>
-__device__ __forceinline__ State<T> global_state(const DevGraph<T>& g) {
-  return {g.p, g.q, g.t, g.s, g.lam, g.z, 0, 0, 0, 0, 0, 0};
-}
-
 // Sum of the edge terms of the P phase, in accumulation type A; the
 // out-edge part is taken from pre when the caller gathered it already.
 template <typename A, typename T, bool kMag>
@@ -405,27 +380,7 @@ hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& s
 template <int kSlots, typename T>
 __device__ __forceinline__ void graph_sweeps(const DevGraph<T>& g, int v0, int v1, int k,
                                              const SweepParams& sp, unsigned char* lds) {
-  const int n = v1 - v0;
-  State<T> st = global_state(g);
-  Q4<T>* lq = reinterpret_cast<Q4<T>*>(lds);
-  P4<T>* lv = reinterpret_cast<P4<T>*>(lds);
-  if (kSlots >= 1) st.p_ = lq, st.pb = v0;
-  if (kSlots >= 2) st.q_ = lq + n, st.qb = v0;
-  if (kSlots >= 3) st.t_ = lv + 2 * n, st.tb = v0;
-  if (kSlots >= 4) st.s_ = lv + 3 * n, st.sb = v0;
-  if (kSlots >= 5) st.lam_ = lq + 4 * n, st.lb = v0;
-  if (kSlots >= 6) st.z_ = lv + 5 * n, st.zb = v0;
-  if (kSlots >= 1) {
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
-      st.p(i) = g.p[i];
-      if (kSlots >= 2) st.q(i) = g.q[i];
-      if (kSlots >= 3) st.t(i) = g.t[i];
-      if (kSlots >= 4) st.s(i) = g.s[i];
-      if (kSlots >= 5) st.lam(i) = g.lam[i];
-      if (kSlots >= 6) st.z(i) = g.z[i];
-    }
-    __syncthreads();
-  }
+  const State<T> st = state_load<kSlots>(g, v0, v1, lds);
   for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<0, T>(g, st, i, sp, false);
   __syncthreads();
   for (int it = 0; it < k; ++it) {
@@ -441,16 +396,7 @@ __device__ __forceinline__ void graph_sweeps(const DevGraph<T>& g, int v0, int v
     }
     __syncthreads();
   }
-  if (kSlots >= 1) {  // each thread writes back the slots only it wrote
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
-      g.p[i] = st.p(i);
-      if (kSlots >= 2) g.q[i] = st.q(i);
-      if (kSlots >= 3) g.t[i] = st.t(i);
-      if (kSlots >= 4) g.s[i] = st.s(i);
-      if (kSlots >= 5) g.lam[i] = st.lam(i);
-      if (kSlots >= 6) g.z[i] = st.z(i);
-    }
-  }
+  state_store<kSlots>(g, st, v0, v1);
 }
 
 template <typename T>
