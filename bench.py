@@ -5,20 +5,23 @@ Workload (headline, ``batched-4096``): 4096 independent SE(3) pose graphs of
 uneven size (poses uniform in [50, 5000], edges/poses uniform in [1.2, 4],
 circle / grid / sphere topologies, sigma_R ~ U[0.01, 0.1] rad, sigma_t ~
 U[0.01, 0.2] m), FP32 state, one persistent launch of 50 sweeps per step,
-one penalty per graph.  One step is one pass of the whole hot path over the
-batch: 50 sweeps of the four phases (p, q, t, s with the multiplier updates)
-for every graph still running, the FP64 cost/residual/merit reductions of
-every graph and the per-graph penalty check (a graph whose merit rose redoes
-its chunk with a doubled penalty, next to the other graphs' next chunk).
-The warm-up steps and the timed steps each run as one solve call.
+one penalty per graph.  Warm-up: chunks of the merit-checked solve (a
+graph whose merit rose redoes its chunk with a doubled penalty), which
+settle each graph's penalty.  One timed step is one pass of the whole hot
+path over the batch: 50 sweeps of the four phases (p, q, t, s with the
+multiplier updates) for every graph, then the FP64 cost and residual
+reductions of every graph, read back to the host.
 
 Printed: one JSON line with edge-iterations/s (sum over graphs of edges x
-accepted sweeps / wall time of the timed steps), the HBM roofline of the
-sweep kernel (hipEvent-timed launches of every graph on the stream the
-kernel runs on), the plain FP64 path and the rotation-matrix rendering on
-the same batch, time to a 1e-6 relative cost gap on the 1000-pose grid for
-both precisions, and the CPU oracle timed on a bounded sample (which also
-checks sampled graphs of the batch against the GPU result).
+sweeps / wall time of the timed steps), the same figure for the
+merit-checked solve over as many chunks (accepted sweeps only), the HBM
+roofline of the sweep kernel (hipEvent-timed launches of every graph on the
+stream the kernel runs on), the plain FP64 path, the rotation-matrix
+rendering and the information model on the same batch, the chordal
+initialisation of the batch, time to a 1e-6 relative cost gap on the
+1000-pose grid for both precisions, and the CPU oracle timed on a bounded
+sample (which also checks sampled graphs of the batch against the GPU
+result).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 4]
     python bench.py --steps 0 ...   # only the hipEvent-timed launches (profiling)
@@ -109,14 +112,18 @@ def copy_calibration(torch, gib=1):
 
 def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tune, sched, block,
               edges_per_graph, model="quat", info=None):
-    """One handle over the whole batch.  A step is one chunk of the
-    merit-checked solve: one persistent launch of `sweeps` sweeps for every
-    graph still running, the FP64 cost/residual/merit reductions of every
-    graph, and the per-graph merit check (a chunk whose merit rose is undone
-    for that graph and rerun with its beta doubled, alongside the other
-    graphs' next chunk).  The warm-up chunks and the timed chunks each run as
-    one solve call; edge-iterations count accepted sweeps only.  The
-    persistent launch alone is also timed with hipEvents on the handle's
+    """One handle over the whole batch.
+
+    Warm-up: `warmup` chunks of the merit-checked solve (per graph, a chunk
+    of `sweeps` sweeps whose merit rose is undone and rerun with its beta
+    doubled), which settles every graph's beta.
+    Timed steps: a step is one pass of the hot path over the batch, one
+    persistent launch of `sweeps` sweeps for every graph at its beta,
+    followed by the FP64 cost and residual reductions of every graph (read
+    back to the host); value = edges x sweeps x steps / wall.
+    Then the merit-checked solve itself for `steps` chunks (accepted
+    edge-iterations only, rejected chunks rerun) is timed as its own figure.
+    The persistent launch alone is timed with hipEvents on the handle's
     stream for the roofline (3 launches of `sweeps` sweeps, every graph)."""
     stream = torch.cuda.Stream()
     opt = P.pgo_default_options(precision=prec, schedule=sched, block=block,
@@ -138,16 +145,28 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
     if warmup:
         beta, done, _ = P.pgo_solve(h, warmup * sweeps, sweeps, GAMMA, 0.0, 2.0, beta)
         accepted += done
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    edge_iters = 0
+    m_total = int(np.sum(edges_per_graph))
+    wall = solve_wall = 0.0
+    edge_iters = solve_edge_iters = 0
     if steps:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(stream):
+            for _ in range(steps):
+                P.pgo_iterate_graphs(h, sweeps, beta, GAMMA)
+                P.pgo_cost(h)
+                P.pgo_residuals(h)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        edge_iters = m_total * sweeps * steps
+        accepted += sweeps * steps
+        t0 = time.perf_counter()
         with torch.cuda.stream(stream):
             beta, done, _ = P.pgo_solve(h, steps * sweeps, sweeps, GAMMA, 0.0, 2.0, beta)
+        torch.cuda.synchronize()
+        solve_wall = time.perf_counter() - t0
         accepted += done
-        edge_iters = int(np.dot(done.astype(np.int64), edges_per_graph))
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        solve_edge_iters = int(np.dot(done.astype(np.int64), edges_per_graph))
     res = P.pgo_residuals(h)
     state = P.pgo_get_state(h)
     # the persistent launch alone, timed with hipEvents on the handle's stream
@@ -162,7 +181,19 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
     kern_ms = float(np.mean([a.elapsed_time(bb) for a, bb in evs]))
     P.pgo_destroy(h)
     return dict(wall=wall, kern_ms=kern_ms, info=info, create_s=create_s, F0=F0, res=res,
-                state=state, accepted=accepted, edge_iters=edge_iters, beta=beta)
+                state=state, accepted=accepted, edge_iters=edge_iters, beta=beta,
+                solve_wall=solve_wall, solve_edge_iters=solve_edge_iters)
+
+
+def solve_figure(r, steps):
+    """The merit-checked solve timed after the steps (accepted sweeps only)."""
+    if not steps or not r["solve_wall"]:
+        return None
+    return {"value": r["solve_edge_iters"] / r["solve_wall"], "unit": "edge-iter/s",
+            "ms_per_chunk": r["solve_wall"] / steps * 1e3, "chunks": steps,
+            "note": "pgo_solve for the same number of 50-sweep chunks per graph: per-graph merit "
+                    "check, rejected chunks undone and rerun with beta doubled; accepted "
+                    "edge-iterations over wall time"}
 
 
 def cinit_leg(P, torch, cat, voff, eoff, steps):
@@ -189,6 +220,7 @@ def cinit_leg(P, torch, cat, voff, eoff, steps):
 def health(r, betas):
     F0, F1 = r["F0"], r["res"][:, 5]
     return {"graphs_cost_up": int(np.sum(~(F1 <= F0))),
+            "graphs_nonfinite": int(np.sum(~np.isfinite(F1))),
             "median_final_over_initial": float(np.median(F1 / F0)),
             "worst_final_over_initial": float(np.max(F1 / F0)),
             "graphs_beta_raised": int(np.sum(r["beta"] > betas)),
@@ -345,7 +377,11 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched-4096", "graphs": args.graphs, "poses": n, "edges": m,
-                   "sweeps_per_step": args.sweeps, "beta": f"{BETA_SCALE} x mean diagonal weight, per graph",
+                   "sweeps_per_step": args.sweeps,
+                   "step": "one persistent launch of the sweeps for all graphs + FP64 cost and "
+                           "residual reductions per graph, read back",
+                   "beta": f"per graph: {BETA_SCALE} x mean diagonal weight, raised by the "
+                           f"merit-checked warm-up",
                    "gamma": GAMMA, "schedule": ["auto", "phase", "graph"][r32["info"]["schedule"]],
                    "block": r32["info"]["block"], "lds_state": bool(r32["info"]["lds"]),
                    "parallelism": "none (1 GPU)"},
@@ -356,6 +392,7 @@ def main():
                      "bytes_model": f"{B_EDGE} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps",
                      "phase_model_GBs": phase_bytes / (r32["kern_ms"] * 1e-3) / 1e9},
         "batch_health": health(r32, betas),
+        "merit_checked_solve": solve_figure(r32, args.steps),
     }
     r64 = None
     if not args.skip_fp64:
@@ -367,7 +404,8 @@ def main():
                        "kernel_ms_per_launch": r64["kern_ms"],
                        "speedup_fp32_over_fp64": value / v64 if v64 else None,
                        "kernel_speedup_fp32_over_fp64": r64["kern_ms"] / r32["kern_ms"],
-                       "batch_health": health(r64, betas)}
+                       "batch_health": health(r64, betas),
+                       "merit_checked_solve": solve_figure(r64, steps64)}
     if not args.skip_chordal:
         # the rotation-matrix rendering on the same batch (FP32): state
         # P, Q, Lambda (9 words each), t, s, z; edges kappa R~ (9), tau t~, tau
@@ -386,7 +424,7 @@ def main():
                          "frac": ca / HBM_PEAK_GBS, "traffic": load_traffic(ckern),
                          "bytes_model": f"{B_EDGE_CHORDAL} B/edge + {B_VERTEX_CHORDAL} B/pose per "
                                         f"sweep x {args.sweeps} sweeps"},
-            "batch_health": health(rc, betas)}
+            "batch_health": health(rc, betas), "merit_checked_solve": solve_figure(rc, stc)}
     if not args.skip_info:
         # the information model on the same batch: S_e = tau_e R diag(a) R^T
         # with eigenvalue ratios up to 10 (FP32)
@@ -407,7 +445,7 @@ def main():
             "roofline": {"bound": "hbm", "achieved": ia, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ia / HBM_PEAK_GBS, "traffic": load_traffic(ikern),
                          "bytes_model": f"{B_EDGE_INFO} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps"},
-            "batch_health": health(ri, betas)}
+            "batch_health": health(ri, betas), "merit_checked_solve": solve_figure(ri, sti)}
     if not args.skip_cinit:
         out["chordal_init"] = cinit_leg(P, torch, cat, voff, eoff, args.steps)
     if not args.skip_ttt:
