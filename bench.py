@@ -9,8 +9,8 @@ one penalty per graph.  Warm-up: chunks of the merit-checked solve (a
 graph whose merit rose redoes its chunk with a doubled penalty), which
 settle each graph's penalty.  One timed step is one pass of the whole hot
 path over the batch: 50 sweeps of the four phases (p, q, t, s with the
-multiplier updates) for every graph, then the FP64 cost and residual
-reductions of every graph, read back to the host.
+multiplier updates) for every graph, then the FP64 cost, residual and merit
+reductions of every graph (one pass), read back to the host.
 
 Printed: one JSON line with edge-iterations/s (sum over graphs of edges x
 sweeps / wall time of the timed steps), the same figure for the
@@ -119,8 +119,9 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
     doubled), which settles every graph's beta.
     Timed steps: a step is one pass of the hot path over the batch, one
     persistent launch of `sweeps` sweeps for every graph at its beta,
-    followed by the FP64 cost and residual reductions of every graph (read
-    back to the host); value = edges x sweeps x steps / wall.
+    followed by the FP64 reductions of every graph (cost, residuals and merit
+    from one pass, read back to the host); value = edges x sweeps x steps /
+    wall.
     Then the merit-checked solve itself for `steps` chunks (accepted
     edge-iterations only, rejected chunks rerun) is timed as its own figure.
     The persistent launch alone is timed with hipEvents on the handle's
@@ -154,8 +155,7 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
         with torch.cuda.stream(stream):
             for _ in range(steps):
                 P.pgo_iterate_graphs(h, sweeps, beta, GAMMA)
-                P.pgo_cost(h)
-                P.pgo_residuals(h)
+                P.pgo_evaluate(h)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         edge_iters = m_total * sweeps * steps
@@ -378,8 +378,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "batched-4096", "graphs": args.graphs, "poses": n, "edges": m,
                    "sweeps_per_step": args.sweeps,
-                   "step": "one persistent launch of the sweeps for all graphs + FP64 cost and "
-                           "residual reductions per graph, read back",
+                   "step": "one persistent launch of the sweeps for all graphs + FP64 cost, "
+                           "residual and merit reductions per graph (one pass), read back",
                    "beta": f"per graph: {BETA_SCALE} x mean diagonal weight, raised by the "
                            f"merit-checked warm-up",
                    "gamma": GAMMA, "schedule": ["auto", "phase", "graph"][r32["info"]["schedule"]],

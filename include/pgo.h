@@ -205,6 +205,17 @@ pgo_status pgo_residuals(pgo_graph* g, double* out);
 pgo_status pgo_merit(pgo_graph* g, double* out);
 
 /*
+ * pgo_evaluate -- pgo_cost, pgo_residuals and pgo_merit from one pass of the
+ * FP64 reductions over the current state (the values are those of the
+ * three calls; one device pass and one synchronisation instead of three).
+ *   F      out, G doubles, or NULL
+ *   res    out, G x 6 doubles (as pgo_residuals), or NULL
+ *   merit  out, G x 2 doubles (as pgo_merit), or NULL
+ * PGO_ENUMERIC if any value is not finite.
+ */
+pgo_status pgo_evaluate(pgo_graph* g, double* F, double* res, double* merit);
+
+/*
  * pgo_solve -- the outer loop of Alg. 1 with the experiments' stopping rule
  * and penalty check, per graph.  Sweeps run in chunks of check_every (one
  * launch per chunk for all graphs still running).  After each chunk, for

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
-    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_solve", "pgo_residuals", "pgo_get_poses",
+    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_evaluate", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
     "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint", "pgo_chordal_init",
@@ -65,6 +65,7 @@ _SIGNATURES = {
     "pgo_iterate_graphs": (C.c_int, [_P, C.c_int32, _D, C.c_double]),
     "pgo_cost": (C.c_int, [_P, _D]),
     "pgo_merit": (C.c_int, [_P, _D]),
+    "pgo_evaluate": (C.c_int, [_P, _D, _D, _D]),
     "pgo_solve": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, _D, _I32,
                             _I32]),
     "pgo_residuals": (C.c_int, [_P, _D]),
@@ -222,6 +223,14 @@ def pgo_merit(h):
     return out
 
 
+def pgo_evaluate(h):
+    """(cost G, residuals G x 6, merit G x 2) from one pass of the reductions."""
+    G = pgo_info(h)["G"]
+    F, res, mer = np.empty(G), np.empty((G, 6)), np.empty((G, 2))
+    _chk(lib().pgo_evaluate(h, _dp(F), _dp(res), _dp(mer)))
+    return F, res, mer
+
+
 def pgo_solve(h, max_sweeps, check_every, gamma, tol, beta_growth, beta):
     """Returns (beta reached, accepted sweeps, converged flags), one per graph."""
     G = pgo_info(h)["G"]
@@ -367,6 +376,9 @@ class PoseGraph:
 
     def merit(self):
         return pgo_merit(self.h)
+
+    def evaluate(self):
+        return pgo_evaluate(self.h)
 
     def solve(self, max_sweeps, check_every, gamma, beta, tol=0.0, beta_growth=2.0):
         return pgo_solve(self.h, max_sweeps, check_every, gamma, tol, beta_growth, beta)

@@ -1075,13 +1075,7 @@ pgo_status pgo_iterate_graphs(pgo_graph* g, int32_t k, const double* beta, doubl
 
 pgo_status pgo_merit(pgo_graph* g, double* out) {
   if (!g || !out) return fail(PGO_EINVAL, "NULL argument");
-  std::vector<double> r;
-  pgo_status s = reduce(g, r);
-  if (s != PGO_OK) return s;
-  for (int32_t k = 0; k < g->G; ++k)
-    merit_of(&r[size_t(kRedVals) * k], g->beta_h[size_t(k)], g->last_gamma, &out[2 * size_t(k)],
-             &out[2 * size_t(k) + 1]);
-  return PGO_OK;
+  return pgo_evaluate(g, nullptr, nullptr, out);
 }
 
 pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, double gamma,
@@ -1172,28 +1166,33 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
 
 pgo_status pgo_cost(pgo_graph* g, double* F) {
   if (!g || !F) return fail(PGO_EINVAL, "NULL argument");
-  std::vector<double> r;
-  pgo_status s = reduce(g, r);
-  if (s != PGO_OK) return s;
-  for (int32_t k = 0; k < g->G; ++k) F[k] = r[size_t(kRedVals) * k + kCost];
-  return PGO_OK;
+  return pgo_evaluate(g, F, nullptr, nullptr);
 }
 
 pgo_status pgo_residuals(pgo_graph* g, double* out) {
   if (!g || !out) return fail(PGO_EINVAL, "NULL argument");
+  return pgo_evaluate(g, nullptr, out, nullptr);
+}
+
+pgo_status pgo_evaluate(pgo_graph* g, double* F, double* res, double* merit) {
+  if (!g) return fail(PGO_EINVAL, "NULL argument");
   std::vector<double> r;
   pgo_status s = reduce(g, r);
   if (s != PGO_OK) return s;
   for (int32_t k = 0; k < g->G; ++k) {
     const double b = g->beta_h[size_t(k)];
     const double* v = &r[size_t(kRedVals) * k];
-    double* o = out + 6 * size_t(k);
-    o[0] = std::sqrt(v[kPQ2]);
-    o[1] = std::sqrt(v[kTS2]);
-    o[2] = (v[kDL2] + v[kDZ2]) / b + b * (v[kDQ2] + v[kDT2]);
-    o[3] = b * std::sqrt(v[kDQ2]);
-    o[4] = b * std::sqrt(v[kDS2]);
-    o[5] = v[kCost];
+    if (F) F[k] = v[kCost];
+    if (res) {
+      double* o = res + 6 * size_t(k);
+      o[0] = std::sqrt(v[kPQ2]);
+      o[1] = std::sqrt(v[kTS2]);
+      o[2] = (v[kDL2] + v[kDZ2]) / b + b * (v[kDQ2] + v[kDT2]);
+      o[3] = b * std::sqrt(v[kDQ2]);
+      o[4] = b * std::sqrt(v[kDS2]);
+      o[5] = v[kCost];
+    }
+    if (merit) merit_of(v, b, g->last_gamma, &merit[2 * size_t(k)], &merit[2 * size_t(k) + 1]);
   }
   return PGO_OK;
 }

@@ -126,3 +126,17 @@ def test_reaches_the_oracle_minimum(pgo):
                 assert F >= F_star * (1 - floor), (prec, F, F_star)
                 best = min(best, F)
         assert best <= F_star * (1 + 1e-6), (prec, best, F_star)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_evaluate_equals_the_three_calls(pgo, prec):
+    """pgo_evaluate (one reduction pass) returns exactly what pgo_cost,
+    pgo_residuals and pgo_merit return."""
+    b = S.batched(4096, first=10, count=4)
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs])
+    with pgo.PoseGraph.from_batch(b, precision=prec) as h:
+        h.iterate(7, betas, GAMMA)
+        F, res, mer = h.evaluate()
+        assert np.array_equal(F, h.cost())
+        assert np.array_equal(res, h.residuals())
+        assert np.array_equal(mer, h.merit())
