@@ -31,6 +31,7 @@ __device__ void polar3(const T a_in[9], T R[9], T sig[3]) {
   const int P[3] = {0, 0, 1}, Qc[3] = {1, 2, 2};
   for (int sweep = 0; sweep < 20; ++sweep) {
     T off = T(0);
+#pragma unroll
     for (int pr = 0; pr < 3; ++pr) {
       const int p = P[pr], q = Qc[pr];
       const T al = c[p][0] * c[p][0] + c[p][1] * c[p][1] + c[p][2] * c[p][2];
@@ -64,7 +65,10 @@ __device__ void polar3(const T a_in[9], T R[9], T sig[3]) {
         R[3 * r + s] = c[0][r] * v[0][s] + c[1][r] * v[1][s] + c[2][r] * v[2][s];
     if (det3(R) > T(0)) break;
     const int kmin = (sig[0] <= sig[1] && sig[0] <= sig[2]) ? 0 : (sig[1] <= sig[2] ? 1 : 2);
-    for (int r = 0; r < 3; ++r) c[kmin][r] = -c[kmin][r];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)  // constant indices keep c in registers
+      if (k == kmin)
+        for (int r = 0; r < 3; ++r) c[k][r] = -c[k][r];
   }
 }
 
