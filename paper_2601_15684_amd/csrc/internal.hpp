@@ -175,12 +175,11 @@ hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const 
                                int G, int k, const SweepParams& sp, int block, int max_n, int lds,
                                hipStream_t st);
 
-// Per-graph snapshot restore: every vertex of a graph with flag[g] != 0 gets
-// its state (p, q, lambda, t, s, z) back from the snapshot arrays.
-// Boundary preparation (prep.hip), FP64.
-// bad[i] = 1 where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
-// device-to-device copy as a kernel (8-byte aligned, size a multiple of 8)
+// Boundary preparation and state transfer (prep.hip), FP64.
+// Device-to-device copy as a kernel (8-byte aligned, size a multiple of 8).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+// Projection onto SO(3) and conversion to a unit quaternion; bad[i] = 1
+// where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
 hipError_t launch_rot_to_quat(const double* R, int64_t count, Q4<double>* out, int canonical,
                               uint8_t* bad, hipStream_t st);
 hipError_t launch_align(const Q4<double>* pv, Q4<double>* qe, const int32_t* ei,
