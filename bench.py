@@ -98,6 +98,17 @@ def load_traffic(kernel):
     return rec["bytes_per_launch"]
 
 
+def measured_rate(kernel, kern_ms):
+    """HBM-side bytes per launch from the committed counters (or None), the
+    rate they give over the measured launch time, and its fraction of peak
+    (the measured-traffic figure; the roofline frac uses algorithmic bytes)."""
+    t = load_traffic(kernel)
+    if t is None:
+        return {"traffic": None}
+    gbs = t / (kern_ms * 1e-3) / 1e9
+    return {"traffic": t, "traffic_GBs": gbs, "traffic_frac": gbs / HBM_PEAK_GBS}
+
+
 def copy_calibration(torch, gib=1):
     """A plain device copy of known size, so that rocprofv3 byte counters can
     be scaled (FETCH_SIZE/WRITE_SIZE of this copy vs its 2 x size bytes)."""
@@ -255,29 +266,67 @@ def reference_minimum(name="grid-1k"):
     return rec["F_star"]
 
 
-def cpu_leg(batch, betas, voff, gpu32, gpu64, budget_s=12.0, sweeps=5):
-    """The FP64 CPU oracle: (1) timed on a bounded sample of the batch,
-    (2) run on sampled small graphs for as many sweeps as the GPU ran, to
-    state the GPU error per result."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_leg(batch, betas, voff, gpu32, gpu64, g1k, beta1k, F_star, budget_s=12.0, sweeps=5):
+    """The FP64 CPU oracle: (1) timed on a bounded sample of the batch, with
+    all of its threads and with one; (2) its time to a 1e-6 relative cost gap
+    on grid-1k (cost checked every 10 sweeps, as the GPU leg); (3) run on
+    sampled small graphs for as many sweeps as the GPU ran, to state the GPU
+    error per result."""
     import torch
 
     from oracle import prep
     from oracle import pradmm as O
-    edges, used, t_total = 0, 0, 0.0
-    for g, b in zip(batch.graphs, betas):
-        Pr, p0, t0 = prep.prepare_graph(g)
-        st = O.init_state(p0, t0)
-        t = time.perf_counter()
-        O.iterate(Pr, st, sweeps, b, GAMMA)
-        t_total += time.perf_counter() - t
-        edges += g.m * sweeps
-        used += 1
-        if t_total > budget_s:
-            break
-    base = dict(value=edges / t_total, unit="edge-iter/s", cores=torch.get_num_threads(),
+
+    def timed(budget):
+        edges, used, t_total = 0, 0, 0.0
+        for g, b in zip(batch.graphs, betas):
+            Pr, p0, t0 = prep.prepare_graph(g)
+            st = O.init_state(p0, t0)
+            t = time.perf_counter()
+            O.iterate(Pr, st, sweeps, b, GAMMA)
+            t_total += time.perf_counter() - t
+            edges += g.m * sweeps
+            used += 1
+            if t_total > budget:
+                break
+        return edges, used, t_total
+
+    threads = torch.get_num_threads()
+    edges, used, t_total = timed(budget_s)
+    torch.set_num_threads(1)
+    try:
+        e1, u1, t1 = timed(budget_s / 3)
+    finally:
+        torch.set_num_threads(threads)
+    base = dict(value=edges / t_total, unit="edge-iter/s", cores=threads,
                 kind="oracle",
                 sample=f"first {used} graphs of the batch, {sweeps} FP64 sweeps each "
-                       f"({edges // sweeps} edges, {t_total:.1f} s of sweep time)")
+                       f"({edges // sweeps} edges, {t_total:.1f} s of sweep time)",
+                cpu=cpu_model(), value_1_thread=e1 / t1,
+                sample_1_thread=f"first {u1} graphs, {sweeps} sweeps each, {t1:.1f} s")
+    if F_star is not None:
+        Pr, p0, t0 = prep.prepare_graph(g1k)
+        st = O.init_state(p0, t0)
+        t = time.perf_counter()
+        done, reached = 0, None
+        while done < 2000:
+            st = O.iterate(Pr, st, 10, beta1k, GAMMA)
+            done += 10
+            if float(O.cost(Pr, st["p"], st["t"])) <= F_star * (1 + 1e-6):
+                reached = time.perf_counter() - t
+                break
+        base["time_to_1e-6"] = {"workload": "grid-1k", "seconds": reached, "sweeps": done,
+                                "cores": threads}
     # sampled parity: the three smallest graphs of the batch whose penalty the
     # merit check left unchanged (the oracle runs the plain iteration)
     order = np.argsort([g.n for g in batch.graphs])
@@ -386,7 +435,7 @@ def main():
                    "block": r32["info"]["block"], "lds_state": bool(r32["info"]["lds"]),
                    "parallelism": "none (1 GPU)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": load_traffic(kname),
+                     "frac": achieved / HBM_PEAK_GBS, **measured_rate(kname, r32["kern_ms"]),
                      "kernel": kname, "kernel_ms_per_launch": r32["kern_ms"],
                      "bytes_per_launch": algo_bytes,
                      "bytes_model": f"{B_EDGE} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps",
@@ -421,7 +470,7 @@ def main():
             "steps": stc, "dtype": "f32", "kernel": ckern,
             "kernel_ms_per_launch": rc["kern_ms"],
             "roofline": {"bound": "hbm", "achieved": ca, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ca / HBM_PEAK_GBS, "traffic": load_traffic(ckern),
+                         "frac": ca / HBM_PEAK_GBS, **measured_rate(ckern, rc["kern_ms"]),
                          "bytes_model": f"{B_EDGE_CHORDAL} B/edge + {B_VERTEX_CHORDAL} B/pose per "
                                         f"sweep x {args.sweeps} sweeps"},
             "batch_health": health(rc, betas), "merit_checked_solve": solve_figure(rc, stc)}
@@ -443,7 +492,7 @@ def main():
             "steps": sti, "dtype": "f32", "kernel": ikern,
             "kernel_ms_per_launch": ri["kern_ms"],
             "roofline": {"bound": "hbm", "achieved": ia, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": ia / HBM_PEAK_GBS, "traffic": load_traffic(ikern),
+                         "frac": ia / HBM_PEAK_GBS, **measured_rate(ikern, ri["kern_ms"]),
                          "bytes_model": f"{B_EDGE_INFO} B/edge + {B_VERTEX} B/pose per sweep x {args.sweeps} sweeps"},
             "batch_health": health(ri, betas), "merit_checked_solve": solve_figure(ri, sti)}
     if not args.skip_cinit:
@@ -460,7 +509,8 @@ def main():
             ttt["speedup_fp32_over_fp64"] = ttt["fp64"]["seconds"] / ttt["fp32"]["seconds"]
         out["time_to_1e-6"] = ttt
     if not args.skip_cpu and args.steps:
-        out["cpu_baseline"] = cpu_leg(batch, betas, voff, r32, r64)
+        out["cpu_baseline"] = cpu_leg(batch, betas, voff, r32, r64, g1k, beta1k,
+                                      None if args.skip_ttt else reference_minimum())
     print(json.dumps(out), flush=True)
 
 
