@@ -67,7 +67,8 @@ typedef enum {
 } pgo_precision;
 
 typedef enum {
-  PGO_SCHED_AUTO = 0,  /* pick by graph sizes (or the autotuner's choice) */
+  PGO_SCHED_AUTO = 0,  /* per graph for at least 256 graphs of at most 8192
+                          poses, else per phase (or the autotuner's choice) */
   PGO_SCHED_PHASE = 1, /* one kernel launch per phase; any graph size */
   PGO_SCHED_GRAPH = 2  /* one persistent workgroup per graph runs all the
                           sweeps of one pgo_iterate call (graphs of at most

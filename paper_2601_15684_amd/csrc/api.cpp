@@ -418,15 +418,19 @@ void choose_default_schedule(pgo_graph* g) {
     g->sched = PGO_SCHED_GRAPH;
   else if (req == PGO_SCHED_PHASE || !graph_ok)
     g->sched = PGO_SCHED_PHASE;
-  else  // auto: one workgroup per graph when graphs are small or numerous
-    g->sched = (g->max_n <= 8192 && (g->G >= 256 || g->n <= 16384)) ? PGO_SCHED_GRAPH
-                                                                      : PGO_SCHED_PHASE;
+  else  // auto: one persistent workgroup per graph fills the GPU only with at
+        // least as many graphs as compute units; fewer or larger graphs
+        // spread every phase over all of them
+    g->sched = (g->max_n <= 8192 && g->G >= 256) ? PGO_SCHED_GRAPH : PGO_SCHED_PHASE;
   if (g->opt.block) {
     g->block_phase = g->opt.block;
     g->block_graph = g->opt.block;
   } else {
     g->block_phase = 256;
-    g->block_graph = (g->max_n >= 2048 && !g->aniso) ? 512 : 256;
+    // per graph: enough threads for one vertex each up to 1024 vertices
+    int b = 64;
+    while (b < g->max_n && b < 1024) b *= 2;
+    g->block_graph = g->aniso ? std::min(b, 256) : b;
   }
 }
 
