@@ -85,7 +85,8 @@ typedef enum {
                             sigma_3 below 1e-2 of the summed term sizes) */
   PGO_MODEL_QUAT_INFO = 2 /* the quaternion model with a full 3x3 translation
                             information matrix per edge (pgo_create_info);
-                            at most 256 threads per workgroup */
+                            at most 256 threads per workgroup (512 in the
+                            per-graph schedule) */
 } pgo_model;
 
 typedef struct {
@@ -264,9 +265,10 @@ pgo_status pgo_get_prepared(pgo_graph* g, double* edge_quat, double* vertex_quat
 
 /* Sizes and settings of the handle; any pointer may be NULL.  lds = 1 when
  * the per-graph schedule keeps each graph's state in LDS for the whole
- * launch as far as it fits, by graph size (quaternion model: p, q, t, s,
- * then the multipliers; chordal model: s, P, t, Q, z, Lambda; within 160
- * KiB per workgroup; chosen by default or by the autotuner). */
+ * launch as far as it fits, by graph size (quaternion and information
+ * models: p, q, t, s, then the multipliers; chordal model: s, P, t, Q, z,
+ * Lambda; within 160 KiB per workgroup; chosen by default or by the
+ * autotuner). */
 pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* precision,
                     int32_t* schedule, int32_t* block, int32_t* model, int32_t* lds);
 

@@ -20,6 +20,8 @@
 // Here G1 x = q_i (x) [0, t~] (x) x^*, G3 x = x (x) [0, t~] (x) p_i^* (Lemma MW),
 // c_e = Im(q (x) [0, t~] (x) p^*) of the edge's tail.  Schedules, fusion of S
 // with the next P and determinism are those of the isotropic sweep.
+#include <algorithm>
+
 #include "internal.hpp"
 
 namespace pgo {
@@ -368,8 +370,9 @@ __device__ __forceinline__ Q4<T> qmul_pure_r(const Q4<T>& a, const V3<T>& b) {  
 // vertex updates
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ void vertex_P_own(const DevAniso<T>& a, int i, const SweepParams& sp, const Q4<T>& qi_,
-                             const P4<T>& si_, const Q4<T>& pi_, const Q4<T>& li_) {
+__device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
+                             const SweepParams& sp, const Q4<T>& qi_, const P4<T>& si_,
+                             const Q4<T>& pi_, const Q4<T>& li_) {
   const DevGraph<T>& g = a.g;
   using A = double;  // the sphere-constrained solve is conditioned by A1's spectrum
   const Q4<A> qi = cvt<A>(qi_);
@@ -382,7 +385,7 @@ __device__ void vertex_P_own(const DevAniso<T>& a, int i, const SweepParams& sp,
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1],
-      [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]], a.o_Sa[e], a.o_Sb[e]}; },
+      [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e]), a.o_Sa[e], a.o_Sb[e]}; },
       [&](const OutE& d) {
         const Sym3<A> S = sym3<A>(d.Sa, d.Sb);
         const V3<A> tm = {A(d.tt.x), A(d.tt.y), A(d.tt.z)};
@@ -396,7 +399,7 @@ __device__ void vertex_P_own(const DevAniso<T>& a, int i, const SweepParams& sp,
     Q4<T> ql, w;
   };
   edge_loop(
-      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{g.q[g.i_nbr[e]], g.i_w[e]}; },
+      g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{st.q(g.i_nbr[e]), g.i_w[e]}; },
       [&](const InE& d) {
         const Q4<A> ql = cvt<A>(d.ql);
         const Q4<A> w = cvt<A>(d.w);
@@ -415,15 +418,15 @@ __device__ void vertex_P_own(const DevAniso<T>& a, int i, const SweepParams& sp,
   const A pp[4] = {pi.w, pi.x, pi.y, pi.z};
   A x[4];
   trs4(M, bv, pp, x);
-  g.p[i] = Q4<T>{T(x[0]), T(x[1]), T(x[2]), T(x[3])};
+  st.p(i) = Q4<T>{T(x[0]), T(x[1]), T(x[2]), T(x[3])};
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, int i, const SweepParams& sp,
-                                         bool save, Q4<T>& lam) {
+__device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, const State<T>& st, int i,
+                                         const SweepParams& sp, bool save) {
   const DevGraph<T>& g = a.g;
-  const Q4<T> pi = g.p[i], qi = g.q[i], li = lam;
-  const V3<T> si = v3(g.s[i]);
+  const Q4<T> pi = st.p(i), qi = st.q(i), li = st.lam(i);
+  const V3<T> si = v3(st.s(i));
   const Q4<T> pic = qconj(pi);
   T M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   T bv[4] = {0, 0, 0, 0};
@@ -436,7 +439,7 @@ __device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, int i, const Swee
       g.o_ptr[i], g.o_ptr[i + 1],
       [&](int e) {
         const int j = g.o_nbr[e];
-        return OutE{g.o_tt[e], g.t[j], a.o_Sa[e], a.o_Sb[e], g.p[j], g.o_w[e]};
+        return OutE{g.o_tt[e], st.t(j), a.o_Sa[e], a.o_Sb[e], st.p(j), g.o_w[e]};
       },
       [&](const OutE& d) {
         const Sym3<T> S = sym3<T>(d.Sa, d.Sb);
@@ -465,14 +468,14 @@ __device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, int i, const Swee
     g.q_prev[i] = qi;
     g.lam_prev[i] = li;
   }
-  g.q[i] = qn;
-  lam = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x), li.y - gb * (pi.y - qn.y),
+  st.q(i) = qn;
+  st.lam(i) = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x), li.y - gb * (pi.y - qn.y),
               li.z - gb * (pi.z - qn.z)};
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_T(const DevAniso<T>& a, int i, const SweepParams& sp,
-                                         bool save, const V3<T>& zi) {
+__device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& st, int i,
+                                         const SweepParams& sp, bool save) {
   const DevGraph<T>& g = a.g;
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
@@ -483,7 +486,7 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, int i, const Swee
       g.i_ptr[i], g.i_ptr[i + 1],
       [&](int e) {
         const int l = g.i_nbr[e];
-        return InE{g.i_tt[e], g.s[l], a.i_Sa[e], a.i_Sb[e], g.q[l], g.p[l]};
+        return InE{g.i_tt[e], st.s(l), a.i_Sa[e], a.i_Sb[e], st.q(l), st.p(l)};
       },
       [&](const InE& d) {
         const V3<T> c = im_mul_conj(qmul_vp(d.ql, V3<T>{d.tt.x, d.tt.y, d.tt.z}), d.pl);
@@ -491,35 +494,37 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, int i, const Swee
             smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.sl.x + c.x, d.sl.y + c.y, d.sl.z + c.z});
         acc.x += y.x; acc.y += y.y; acc.z += y.z;
       });
-  const P4<T> ti = g.t[i], si = g.s[i];
+  const P4<T> ti = st.t(i), si = st.s(i);
+  const V3<T> zi = v3(st.z(i));
   const T b = T(sp.beta), h = T(sp.h3);
   const V3<T> rhs = {T(2) * acc.x + b * si.x + zi.x + h * ti.x, T(2) * acc.y + b * si.y + zi.y + h * ti.y,
                      T(2) * acc.z + b * si.z + zi.z + h * ti.z};
   if (save) g.t_prev[i] = ti;
-  g.t[i] = pad3(sym_solve3(sym3<T>(a.cTa[i], a.cTb[i]), b + h, rhs));
+  st.t(i) = pad3(sym_solve3(sym3<T>(a.cTa[i], a.cTb[i]), b + h, rhs));
 }
 
 template <typename T>
-__device__ __forceinline__ void vertex_S(const DevAniso<T>& a, int i, const SweepParams& sp,
-                                         bool save, V3<T>& z, Q4<T>* p_out = nullptr,
-                                         Q4<T>* q_out = nullptr, P4<T>* s_out = nullptr) {
+__device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& st, int i,
+                                         const SweepParams& sp, bool save,
+                                         Q4<T>* p_out = nullptr, Q4<T>* q_out = nullptr,
+                                         P4<T>* s_out = nullptr) {
   const DevGraph<T>& g = a.g;
-  const Q4<T> pi = g.p[i], qi = g.q[i];
+  const Q4<T> pi = st.p(i), qi = st.q(i);
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
     P4<T> tt, tj, Sa, Sb;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1],
-      [&](int e) { return OutE{g.o_tt[e], g.t[g.o_nbr[e]], a.o_Sa[e], a.o_Sb[e]}; },
+      [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e]), a.o_Sa[e], a.o_Sb[e]}; },
       [&](const OutE& d) {
         const V3<T> c = im_mul_conj(qmul_vp(qi, V3<T>{d.tt.x, d.tt.y, d.tt.z}), pi);
         const V3<T> y =
             smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.tj.x - c.x, d.tj.y - c.y, d.tj.z - c.z});
         acc.x += y.x; acc.y += y.y; acc.z += y.z;
       });
-  const P4<T> ti = g.t[i], si = g.s[i];
-  const V3<T> zi = z;
+  const P4<T> ti = st.t(i), si = st.s(i);
+  const V3<T> zi = v3(st.z(i));
   const T b = T(sp.beta), h = T(sp.h4);
   const V3<T> rhs = {T(2) * acc.x + b * ti.x - zi.x + h * si.x, T(2) * acc.y + b * ti.y - zi.y + h * si.y,
                      T(2) * acc.z + b * ti.z - zi.z + h * si.z};
@@ -529,8 +534,9 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, int i, const Swee
     g.s_prev[i] = si;
     g.z_prev[i] = pad3(zi);
   }
-  g.s[i] = pad3(sn);
-  z = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  st.s(i) = pad3(sn);
+  st.z(i) = pad3(V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
+                       zi.z - gb * (ti.z - sn.z)});
   if (p_out) {
     *p_out = pi;
     *q_out = qi;
@@ -539,28 +545,17 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, int i, const Swee
 }
 
 template <int PH, typename T>
-__device__ __forceinline__ void phase_a(const DevAniso<T>& a, int i, const SweepParams& sp,
-                                        bool save) {
-  const DevGraph<T>& g = a.g;
-  if (PH == 0) vertex_P_own(a, i, sp, g.q[i], g.s[i], g.p[i], g.lam[i]);
-  if (PH == 1) {
-    Q4<T> l = g.lam[i];
-    vertex_Q(a, i, sp, save, l);
-    g.lam[i] = l;
-  }
-  if (PH == 2) vertex_T(a, i, sp, save, v3(g.z[i]));
-  if (PH == 3) {
-    V3<T> z = v3(g.z[i]);
-    vertex_S(a, i, sp, save, z);
-    g.z[i] = pad3(z);
-  }
+__device__ __forceinline__ void phase_a(const DevAniso<T>& a, const State<T>& st, int i,
+                                        const SweepParams& sp, bool save) {
+  if (PH == 0) vertex_P_own(a, st, i, sp, st.q(i), st.s(i), st.p(i), st.lam(i));
+  if (PH == 1) vertex_Q(a, st, i, sp, save);
+  if (PH == 2) vertex_T(a, st, i, sp, save);
+  if (PH == 3) vertex_S(a, st, i, sp, save);
   if (PH == 4) {  // S of this sweep + P of the next
-    V3<T> z = v3(g.z[i]);
     Q4<T> pi, qi;
     P4<T> si;
-    vertex_S(a, i, sp, false, z, &pi, &qi, &si);
-    g.z[i] = pad3(z);
-    vertex_P_own(a, i, sp, qi, si, pi, g.lam[i]);
+    vertex_S(a, st, i, sp, false, &pi, &qi, &si);
+    vertex_P_own(a, st, i, sp, qi, si, pi, st.lam(i));
   }
 }
 
@@ -583,30 +578,58 @@ __global__ void __launch_bounds__(kMaxBlockA) k_phase_a(DevAniso<T> a, SweepPara
   if (i >= a.g.n) return;
   if (sp.active && !sp.active[a.g.gid[i]]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[a.g.gid[i]];
-  phase_a<PH, T>(a, i, sp, save != 0);
+  phase_a<PH, T>(a, global_state(a.g), i, sp, save != 0);
+}
+
+// One persistent workgroup per graph with the LDS residency of the
+// quaternion sweep: a graph keeps the first k of p, q, t, s, lambda, z in
+// LDS for the whole launch, k the most whose slots fit.  Up to 512 threads:
+// the P update's registers allow eight waves per CU, so one 512-thread
+// workgroup with all of the CU's LDS runs as many waves as two 256-thread
+// ones would.
+constexpr int kMaxBlockGraphA = 512;
+
+template <int kSlots, typename T>
+__device__ __forceinline__ void graph_sweeps_a(const DevAniso<T>& a, int v0, int v1, int k,
+                                               const SweepParams& sp, unsigned char* lds) {
+  const State<T> st = state_load<kSlots>(a.g, v0, v1, lds);
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<0, T>(a, st, i, sp, false);
+  __syncthreads();
+  for (int it = 0; it < k; ++it) {
+    const bool save = it == k - 1;
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<1, T>(a, st, i, sp, save);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<2, T>(a, st, i, sp, save);
+    __syncthreads();
+    if (save) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<3, T>(a, st, i, sp, true);
+    } else {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<4, T>(a, st, i, sp, false);
+    }
+    __syncthreads();
+  }
+  state_store<kSlots>(a.g, st, v0, v1);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kMaxBlockA) k_graph_sweeps_a(DevAniso<T> a, const int32_t* __restrict__ voff,
-                                 const int32_t* __restrict__ order, int k, SweepParams sp) {
+__global__ void __launch_bounds__(kMaxBlockGraphA) k_graph_sweeps_a(
+    DevAniso<T> a, const int32_t* __restrict__ voff, const int32_t* __restrict__ order, int k,
+    SweepParams sp, int lds_bytes) {
+  extern __shared__ unsigned char lds_raw[];
   const int gr = order[blockIdx.x];
   const int v0 = voff[gr], v1 = voff[gr + 1];
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
-  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<0, T>(a, i, sp, false);
-  __syncthreads();
-  for (int it = 0; it < k; ++it) {
-    const bool save = it == k - 1;
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<1, T>(a, i, sp, save);
-    __syncthreads();
-    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<2, T>(a, i, sp, save);
-    __syncthreads();
-    if (save) {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<3, T>(a, i, sp, true);
-    } else {
-      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase_a<4, T>(a, i, sp, false);
-    }
-    __syncthreads();
+  const size_t per = size_t(v1 - v0) * sizeof(Q4<T>);
+  const int slots = int(std::min<size_t>(6, size_t(lds_bytes) / per));
+  switch (slots) {
+    case 6: graph_sweeps_a<6, T>(a, v0, v1, k, sp, lds_raw); break;
+    case 5: graph_sweeps_a<5, T>(a, v0, v1, k, sp, lds_raw); break;
+    case 4: graph_sweeps_a<4, T>(a, v0, v1, k, sp, lds_raw); break;
+    case 3: graph_sweeps_a<3, T>(a, v0, v1, k, sp, lds_raw); break;
+    case 2: graph_sweeps_a<2, T>(a, v0, v1, k, sp, lds_raw); break;
+    case 1: graph_sweeps_a<1, T>(a, v0, v1, k, sp, lds_raw); break;
+    default: graph_sweeps_a<0, T>(a, v0, v1, k, sp, lds_raw); break;
   }
 }
 
@@ -675,10 +698,21 @@ hipError_t launch_phase_sweeps_a(const DevAniso<T>& a, int k, const SweepParams&
 
 template <typename T>
 hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, const int32_t* order,
-                                 int G, int k, const SweepParams& sp, int block, hipStream_t st) {
+                                 int G, int k, const SweepParams& sp, int block, int max_n, int lds,
+                                 hipStream_t st) {
   if (G <= 0 || k <= 0) return hipSuccess;
-  if (block <= 0 || block > kMaxBlockA || block % 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((k_graph_sweeps_a<T>), dim3(G), dim3(block), 0, st, a, voff, order, k, sp);
+  if (block <= 0 || block > kMaxBlockGraphA || block % 64) return hipErrorInvalidValue;
+  // all six arrays of the largest graph, within the 160 KiB of a CU
+  constexpr size_t kLds = 160 * 1024;
+  size_t bytes = lds ? std::min(kLds, 6 * sizeof(Q4<T>) * size_t(max_n)) : 0;
+  if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_a<T>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   int(bytes)) != hipSuccess) {
+    (void)hipGetLastError();  // clear a refused request; run without LDS residency
+    bytes = 0;
+  }
+  hipLaunchKernelGGL((k_graph_sweeps_a<T>), dim3(G), dim3(block), bytes, st, a, voff, order, k,
+                     sp, int(bytes));
   return hipGetLastError();
 }
 
@@ -706,7 +740,7 @@ hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t
                                                hipStream_t);                                      \
   template hipError_t launch_graph_sweeps_a<T>(const DevAniso<T>&, const int32_t*,               \
                                                const int32_t*, int, int, const SweepParams&,      \
-                                               int, hipStream_t);                                 \
+                                               int, int, int, hipStream_t);                       \
   template hipError_t launch_fill_edges_a<T>(const int32_t*, const double*, const double*,       \
                                              int64_t, P4<T>*, P4<T>*, P4<T>*, hipStream_t);       \
   template hipError_t launch_vertex_consts_a<T>(int32_t, const int32_t*, const int32_t*,         \

@@ -204,11 +204,9 @@ DevChordal<T> viewc(const pgo_graph* g) {
 }
 
 // Whether the per-graph kernel can keep graphs' state in LDS for a launch
-// (quaternion and chordal models; each graph keeps what fits, see
-// launch_graph_sweeps and launch_graph_sweeps_c).  The information model's
-// P update leaves registers for two 256-thread workgroups per CU, and
-// sharing the LDS between them measured slower than none.
-bool lds_fits(const pgo_graph* g) { return !g->aniso; }
+// (every model; each graph keeps what fits, see launch_graph_sweeps,
+// launch_graph_sweeps_c and launch_graph_sweeps_a).
+bool lds_fits(const pgo_graph*) { return true; }
 
 template <typename T>
 DevAniso<T> viewa(const pgo_graph* g) {
@@ -242,8 +240,10 @@ pgo_status check_options(const pgo_options& o) {
     return fail(PGO_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
   if (o.model != PGO_MODEL_QUAT && o.model != PGO_MODEL_CHORDAL && o.model != PGO_MODEL_QUAT_INFO)
     return fail(PGO_EINVAL, "model must be PGO_MODEL_QUAT, PGO_MODEL_CHORDAL or PGO_MODEL_QUAT_INFO");
-  if (o.model == PGO_MODEL_QUAT_INFO && o.block > 256)
-    return fail(PGO_EINVAL, "the information model runs at most 256 threads per workgroup");
+  if (o.model == PGO_MODEL_QUAT_INFO && o.block > (o.schedule == PGO_SCHED_GRAPH ? 512 : 256))
+    return fail(PGO_EINVAL,
+                "the information model runs at most 256 threads per workgroup (512 in the "
+                "per-graph schedule)");
   return PGO_OK;
 }
 
@@ -430,7 +430,7 @@ void choose_default_schedule(pgo_graph* g) {
     // per graph: enough threads for one vertex each up to 1024 vertices
     int b = 64;
     while (b < g->max_n && b < 1024) b *= 2;
-    g->block_graph = g->aniso ? std::min(b, 256) : b;
+    g->block_graph = g->aniso ? std::min(b, 512) : b;
   }
 }
 
@@ -625,7 +625,8 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
       HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->max_n,
                                       g->graph_lds, g->stream));
     else if (g->aniso)
-      HIPCHK(launch_graph_sweeps_a<T>(da, g->voff32, g->order, g->G, k, sp, block, g->stream));
+      HIPCHK(launch_graph_sweeps_a<T>(da, g->voff32, g->order, g->G, k, sp, block, g->max_n,
+                                      g->graph_lds, g->stream));
     else
       HIPCHK(launch_graph_sweeps<T>(d, g->voff32, g->order, g->G, k, sp, block, g->max_n,
                                     g->graph_lds, g->stream));
@@ -1293,12 +1294,12 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
     int sched, block, lds;
   };
   std::vector<Cand> cands;
-  const int bmax = g->aniso ? 256 : 1024;
+  const int bmax = g->aniso ? 256 : 1024, bmax_graph = g->aniso ? 512 : 1024;
   for (int b : {64, 128, 256, 512})
     if (b <= bmax) cands.push_back({PGO_SCHED_PHASE, b, 0});
   if (g->max_n <= PGO_GRAPH_SCHED_MAX_N)
     for (int b : {128, 256, 512, 1024}) {
-      if (b > bmax) continue;
+      if (b > bmax_graph) continue;
       cands.push_back({PGO_SCHED_GRAPH, b, 0});
       if (lds_fits(g)) cands.push_back({PGO_SCHED_GRAPH, b, 1});
     }

@@ -228,8 +228,11 @@ template <typename T>
 hipError_t launch_phase_sweeps_a(const DevAniso<T>& a, int k, const SweepParams& sp, int block,
                                  hipStream_t st);
 template <typename T>
+// lds != 0: each graph keeps the part of its state that fits in LDS there
+// for the whole launch (as launch_graph_sweeps); block <= 512.
 hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, const int32_t* order,
-                                 int G, int k, const SweepParams& sp, int block, hipStream_t st);
+                                 int G, int k, const SweepParams& sp, int block, int max_n, int lds,
+                                 hipStream_t st);
 template <typename T>
 hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const double* S9, int64_t m,
                                P4<T>* tt, P4<T>* Sa, P4<T>* Sb, hipStream_t st);
