@@ -482,7 +482,7 @@ def main():
         ri = run_batch(P, torch, cat, voff, eoff, "fp32", betas, args.sweeps, sti,
                        max(1, args.warmup // 2) if args.steps else 0, tune,
                        "auto" if args.schedule == "auto" else args.schedule,
-                       min(args.block, 256), epg, info=info)
+                       min(args.block, 512 if args.schedule == "graph" else 256), epg, info=info)
         del info
         ib = (B_EDGE_INFO * m + B_VERTEX * n) * args.sweeps
         ia = ib / (ri["kern_ms"] * 1e-3) / 1e9
