@@ -318,3 +318,35 @@ def test_graph_replays_equal_eager_launches(pgo, prec):
             h.iterate(5, beta, GAMMA)
             h.cost()
             assert np.array_equal(h.state(), eager)
+
+
+def test_lds_residency_thresholds_bitwise(pgo):
+    """Graphs on both sides of every LDS residency threshold of the per-graph
+    kernel (160 KiB of 16-byte FP32 slots: all six state arrays up to 1706
+    poses, five to 2048, four to 2560, three to 3413, two to 5120, one
+    above; FP64 slots are twice as wide; the chordal model's arrays have
+    their own widths) give the same bits as the per-phase schedule, whose
+    state stays in memory, for every model and both precisions."""
+    sizes = [1706, 1707, 2048, 2049, 2560, 2561, 3413, 3414, 5120, 5121]
+    graphs = [S.circle(n, n_closures=n // 2, sigma_R=0.05, sigma_t=0.05, seed=k)
+              for k, n in enumerate(sizes)]
+    b = S.Batch(graphs)
+    betas = np.array([0.05 * abar(gr) for gr in graphs])
+    voff, _ = b.offsets()
+    infos = np.concatenate([S.random_info(gr.m, gr.tau, 10.0, seed=k) for k, gr in enumerate(graphs)])
+    for model in ("quat", "chordal", "info"):
+        for prec in ("fp32", "fp64"):
+            got = {}
+            for sched, block in (("phase", 256), ("graph", 512 if model == "info" else 1024)):
+                kw = dict(precision=prec, schedule=sched, block=block)
+                if model == "info":
+                    h = pgo.PoseGraph.from_batch(b, info=infos, **kw)
+                else:
+                    h = pgo.PoseGraph.from_batch(b, model=model, **kw)
+                with h:
+                    h.iterate(6, betas, GAMMA)
+                    got[sched] = h.state()
+                    if sched == "graph":
+                        assert h.info()["lds"] == 1
+            assert np.array_equal(got["phase"], got["graph"]), (model, prec)
+            assert np.isfinite(got["graph"]).all()
