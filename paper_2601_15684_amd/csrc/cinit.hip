@@ -160,7 +160,9 @@ __global__ void __launch_bounds__(kCB) k_cinit_Ap(CinitGraph c, CinitVec v,
   if (threadIdx.x == 0) part[ch] = acc;
 }
 
-// x += alpha p, r -= alpha ap, z = r / d; partial of <r, z>
+// x += alpha p, r -= alpha ap, z = r / d; partial of <r, z>.  The chunk's
+// W x (vertices) doubles are walked as one flat range, so consecutive
+// threads touch consecutive doubles.
 template <int W>
 __global__ void __launch_bounds__(kCB) k_cinit_update(CinitGraph c, CinitVec v,
                                                       const int64_t* __restrict__ beg,
@@ -175,25 +177,23 @@ __global__ void __launch_bounds__(kCB) k_cinit_update(CinitGraph c, CinitVec v,
   const int gr = cgraph[ch];
   if (active[gr]) {
     const double a = alpha[gr];
-    for (int64_t i = beg[ch] + threadIdx.x; i < end[ch]; i += kCB) {
+    for (int64_t q = W * beg[ch] + threadIdx.x; q < W * end[ch]; q += kCB) {
+      const int64_t i = q / W;
       const double di = c.diag[i];
       const bool fr = !c.anchor[i];
-      for (int k = 0; k < W; ++k) {
-        const int64_t q = W * i + k;
-        v.x[q] += a * v.p[q];
-        const double r = v.r[q] - a * v.ap[q];
-        v.r[q] = r;
-        const double z = (fr && di > 0.0) ? r / di : 0.0;
-        v.z[q] = z;
-        acc += r * z;
-      }
+      v.x[q] += a * v.p[q];
+      const double r = v.r[q] - a * v.ap[q];
+      v.r[q] = r;
+      const double z = (fr && di > 0.0) ? r / di : 0.0;
+      v.z[q] = z;
+      acc += r * z;
     }
   }
   acc = block_sum1(acc, sh);
   if (threadIdx.x == 0) part[ch] = acc;
 }
 
-// p = z + beta p
+// p = z + beta p, over the chunk's doubles as one flat range
 template <int W>
 __global__ void __launch_bounds__(kCB) k_cinit_dir(CinitVec v, const int64_t* __restrict__ beg,
                                                    const int64_t* __restrict__ end,
@@ -204,11 +204,7 @@ __global__ void __launch_bounds__(kCB) k_cinit_dir(CinitVec v, const int64_t* __
   const int gr = cgraph[ch];
   if (!active[gr]) return;
   const double b = beta[gr];
-  for (int64_t i = beg[ch] + threadIdx.x; i < end[ch]; i += kCB)
-    for (int k = 0; k < W; ++k) {
-      const int64_t q = W * i + k;
-      v.p[q] = v.z[q] + b * v.p[q];
-    }
+  for (int64_t q = W * beg[ch] + threadIdx.x; q < W * end[ch]; q += kCB) v.p[q] = v.z[q] + b * v.p[q];
 }
 
 // per-graph scalars.  mode 0: rz0 = rz = sum, active = rz > 0.
