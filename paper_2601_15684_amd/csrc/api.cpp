@@ -1479,8 +1479,13 @@ pgo_status pgo_chordal_init(pgo_graph* g, int32_t max_iters, double tol, int32_t
     HIPCHK(launch_cinit_qmat(m, g->qe, R9, st));
     HIPCHK(launch_cinit_qmat(n, g->p0, given, st));
   }
-  CinitGraph c{g->o_ptr, g->o_nbr, g->o_perm, g->i_ptr, g->i_nbr, g->i_perm,
-               g->kappa, R9, g->tm, diag, d_anchor};
+  double *o_wR = nullptr, *i_wR = nullptr, *o_w = nullptr, *i_w = nullptr;
+  if ((s = talloc(reinterpret_cast<void**>(&o_wR), 72 * mm)) != PGO_OK) return cleanup(s);
+  if ((s = talloc(reinterpret_cast<void**>(&i_wR), 72 * mm)) != PGO_OK) return cleanup(s);
+  if ((s = talloc(reinterpret_cast<void**>(&o_w), 8 * mm)) != PGO_OK) return cleanup(s);
+  if ((s = talloc(reinterpret_cast<void**>(&i_w), 8 * mm)) != PGO_OK) return cleanup(s);
+  CinitGraph c{g->o_ptr, g->o_nbr, g->o_perm, g->i_ptr, g->i_nbr, g->i_perm, g->kappa, R9,
+               g->tm, diag, d_anchor, o_wR, i_wR, o_w, i_w};
   CinitVec v{vec[0], vec[1], vec[2], vec[3], vec[4]};
   CinitChunks ch{d_cb, d_ce, d_cgr, d_goff, int(cb.size()), part};
   CinitScalars S{sc[0], sc[1], sc[2], sc[3], act, its};
@@ -1488,6 +1493,7 @@ pgo_status pgo_chordal_init(pgo_graph* g, int32_t max_iters, double tol, int32_t
   // 1. relaxed rotations from the given ones
   HIPCHK(launch_copy(v.x, given, 72 * size_t(n), st));
   HIPCHK(launch_cinit_diag(c, int32_t(n), st));
+  HIPCHK(launch_cinit_edges(c, m, 9, st));
   hipError_t he = launch_cinit_cg(c, v, ch, 9, nullptr, max_iters, 32, tol, S, G, hact.data(), st);
   if (he != hipSuccess) return cleanup(hip_fail(he, "chordal init (rotations)"));
   std::vector<int32_t> h1(static_cast<size_t>(G));
@@ -1498,6 +1504,7 @@ pgo_status pgo_chordal_init(pgo_graph* g, int32_t max_iters, double tol, int32_t
   c.wt = g->tau;
   HIPCHK(launch_copy(v.x, g->t0dev, 24 * size_t(n), st));
   HIPCHK(launch_cinit_diag(c, int32_t(n), st));
+  HIPCHK(launch_cinit_edges(c, m, 3, st));
   HIPCHK(launch_cinit_rhs_t(c, int32_t(n), Rp, rhs, st));
   he = launch_cinit_cg(c, v, ch, 3, rhs, max_iters, 32, tol, S, G, hact.data(), st);
   if (he != hipSuccess) return cleanup(hip_fail(he, "chordal init (translations)"));

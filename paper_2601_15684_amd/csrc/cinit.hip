@@ -46,32 +46,46 @@ __device__ void apply_A(const CinitGraph& c, int i, const double* __restrict__ x
   const double di = c.diag[i];
   for (int k = 0; k < W; ++k) y[k] = di * xi[k];
   for (int e = c.o_ptr[i]; e < c.o_ptr[i + 1]; ++e) {
-    const int64_t ed = c.o_perm[e];
     const double* xj = x + int64_t(W) * c.o_nbr[e];
-    const double w = c.wt[ed];
     if (W == 9) {
-      const double* Rm = c.R9 + 9 * ed;  // x_j R~^T: (r, q) -> sum_k x_j[r][k] R~[q][k]
+      const double* Rm = c.o_wR + 9 * int64_t(e);  // x_j (w R~)^T: (r, q) -> sum_k x_j[r][k] wR~[q][k]
       for (int r = 0; r < 3; ++r)
         for (int q = 0; q < 3; ++q)
-          y[3 * r + q] -= w * (xj[3 * r] * Rm[3 * q] + xj[3 * r + 1] * Rm[3 * q + 1] +
-                               xj[3 * r + 2] * Rm[3 * q + 2]);
+          y[3 * r + q] -= xj[3 * r] * Rm[3 * q] + xj[3 * r + 1] * Rm[3 * q + 1] +
+                          xj[3 * r + 2] * Rm[3 * q + 2];
     } else {
+      const double w = c.o_w[e];
       for (int k = 0; k < W; ++k) y[k] -= w * xj[k];
     }
   }
   for (int e = c.i_ptr[i]; e < c.i_ptr[i + 1]; ++e) {
-    const int64_t ed = c.i_perm[e];
     const double* xl = x + int64_t(W) * c.i_nbr[e];
-    const double w = c.wt[ed];
     if (W == 9) {
-      const double* Rm = c.R9 + 9 * ed;  // x_l R~: (r, q) -> sum_k x_l[r][k] R~[k][q]
+      const double* Rm = c.i_wR + 9 * int64_t(e);  // x_l (w R~): (r, q) -> sum_k x_l[r][k] wR~[k][q]
       for (int r = 0; r < 3; ++r)
         for (int q = 0; q < 3; ++q)
-          y[3 * r + q] -= w * (xl[3 * r] * Rm[q] + xl[3 * r + 1] * Rm[3 + q] +
-                               xl[3 * r + 2] * Rm[6 + q]);
+          y[3 * r + q] -= xl[3 * r] * Rm[q] + xl[3 * r + 1] * Rm[3 + q] + xl[3 * r + 2] * Rm[6 + q];
     } else {
+      const double w = c.i_w[e];
       for (int k = 0; k < W; ++k) y[k] -= w * xl[k];
     }
+  }
+}
+
+// edge data of the operator in out- and in-order
+__global__ void k_cinit_edges(CinitGraph c, int64_t m, int W) {
+  const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= m) return;
+  const int64_t eo = c.o_perm[e], ei = c.i_perm[e];
+  if (W == 9) {
+    const double wo = c.wt[eo], wi = c.wt[ei];
+    for (int k = 0; k < 9; ++k) {
+      c.o_wR[9 * e + k] = wo * c.R9[9 * eo + k];
+      c.i_wR[9 * e + k] = wi * c.R9[9 * ei + k];
+    }
+  } else {
+    c.o_w[e] = c.wt[eo];
+    c.i_w[e] = c.wt[ei];
   }
 }
 
@@ -267,6 +281,13 @@ __global__ void k_cinit_qmat(int64_t m, const Q4<double>* __restrict__ q, double
 inline dim3 grid_of(int64_t count, int block) { return dim3(unsigned((count + block - 1) / block)); }
 
 }  // namespace
+
+hipError_t launch_cinit_edges(const CinitGraph& c, int64_t m, int W, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  if (W != 9 && W != 3) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cinit_edges, dim3(unsigned((m + 255) / 256)), dim3(256), 0, st, c, m, W);
+  return hipGetLastError();
+}
 
 hipError_t launch_cinit_diag(const CinitGraph& c, int32_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;

@@ -289,11 +289,18 @@ struct CinitGraph {
   const int32_t* i_ptr;
   const int32_t* i_nbr;
   const int32_t* i_perm;
-  const double* wt;       // kappa (rotations) or tau (translations)
-  const double* R9;       // measured rotations, m x 9 row-major
-  const double* tm;       // m x 3
+  const double* wt;       // kappa (rotations) or tau (translations), caller order
+  const double* R9;       // measured rotations, m x 9 row-major, caller order
+  const double* tm;       // m x 3, caller order
   double* diag;           // n: sum of the weights at each vertex
   const uint8_t* anchor;  // n: 1 = held at its given value
+  // the operator's edge data in out- and in-order (so a vertex reads its
+  // edges contiguously): weight x R~ (m x 9) for the rotation solve, the
+  // weight alone for the translation solve
+  double* o_wR;
+  double* i_wR;
+  double* o_w;
+  double* i_w;
 };
 struct CinitVec {  // W doubles per vertex each
   double* x;
@@ -319,6 +326,8 @@ struct CinitScalars {  // one per graph
   int32_t* iters;
 };
 hipError_t launch_cinit_diag(const CinitGraph& c, int32_t n, hipStream_t st);
+// fills o_wR, i_wR (W = 9) or o_w, i_w (W = 3) from wt, R9 and the permutations
+hipError_t launch_cinit_edges(const CinitGraph& c, int64_t m, int W, hipStream_t st);
 hipError_t launch_cinit_rhs_t(const CinitGraph& c, int32_t n, const double* R, double* rhs,
                               hipStream_t st);
 hipError_t launch_cinit_project(int32_t n, const uint8_t* anchor, const double* X,
