@@ -18,8 +18,9 @@ merit-checked solve over as many chunks (accepted sweeps only), the HBM
 roofline of the sweep kernel (hipEvent-timed launches of every graph on the
 stream the kernel runs on), the plain FP64 path, the rotation-matrix
 rendering and the information model on the same batch, the chordal
-initialisation of the batch, time to a 1e-6 relative cost gap on the
-1000-pose grid for both precisions, and the CPU oracle timed on a bounded
+initialisation of the batch, the differentiation workload (forward and
+hand-written adjoint of 50 unrolled sweeps of the 20000-pose grid), time to
+a 1e-6 relative cost gap on the 1000-pose grid for both precisions, and the CPU oracle timed on a bounded
 sample (which also checks sampled graphs of the batch against the GPU
 result).
 
@@ -228,6 +229,43 @@ def cinit_leg(P, torch, cat, voff, eoff, steps):
             "median_cost_chordal_over_odometry": float(np.median(F_ch / F_odo))}
 
 
+def adjoint_leg(P, torch, reps=3):
+    """The differentiation workload (diff-20k, K = 50 unrolled sweeps,
+    checkpoints every C = 10): forward, the loss sum |t_i - t_i^gt|^2 and the
+    hand-written adjoint into kappa, tau, t~ and the rotation perturbation,
+    through the torch.autograd.Function; wall time per forward + backward."""
+    from paper_2601_15684_amd.autograd import unrolled_pradmm
+    g = S.make_config("diff-20k")
+    beta = BETA_SCALE * abar(g)
+    K, C = 50, 10
+    out = {"workload": "diff-20k", "poses": g.n, "edges": g.m, "K": K, "C": C}
+
+    def leaf(x):
+        return torch.as_tensor(np.ascontiguousarray(x), dtype=torch.float64,
+                               device="cuda").requires_grad_()
+
+    t_gt = torch.as_tensor(g.t_gt, dtype=torch.float64, device="cuda")
+    for prec in ("fp32", "fp64"):
+        with P.PoseGraph.from_graph(g, precision=prec) as h:
+            ms = []
+            for rep in range(reps + 1):
+                kappa, tau, tm, om = leaf(g.kappa), leaf(g.tau), leaf(g.tm), leaf(np.zeros((g.m, 3)))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                state = unrolled_pradmm(h, kappa, tau, tm, om, K, beta, GAMMA, C)
+                loss = ((state[:, 8:11] - t_gt) ** 2).sum()
+                loss.backward()
+                torch.cuda.synchronize()
+                if rep:  # the first call builds the captured launch sequences
+                    ms.append((time.perf_counter() - t0) * 1e3)
+        out[prec] = {"ms_forward_and_adjoint": float(np.mean(ms)),
+                     "edge_iters_per_s": g.m * K / (np.mean(ms) * 1e-3)}
+    out["speedup_fp32_over_fp64"] = (out["fp64"]["ms_forward_and_adjoint"] /
+                                     out["fp32"]["ms_forward_and_adjoint"])
+    out["note"] = "edge_iters_per_s counts the K forward sweeps per forward + adjoint"
+    return out
+
+
 def health(r, betas):
     F0, F1 = r["F0"], r["res"][:, 5]
     return {"graphs_cost_up": int(np.sum(~(F1 <= F0))),
@@ -371,6 +409,7 @@ def main():
     ap.add_argument("--skip-cinit", action="store_true", help="skip the chordal-initialisation leg")
     ap.add_argument("--skip-info", action="store_true", help="skip the information-model leg")
     ap.add_argument("--skip-ttt", action="store_true", help="skip the time-to-tolerance leg")
+    ap.add_argument("--skip-adjoint", action="store_true", help="skip the differentiation leg")
     ap.add_argument("--no-tune", action="store_true", help="use --schedule/--block as given")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phase", "graph"])
     ap.add_argument("--block", type=int, default=0)
@@ -497,6 +536,8 @@ def main():
             "batch_health": health(ri, betas), "merit_checked_solve": solve_figure(ri, sti)}
     if not args.skip_cinit:
         out["chordal_init"] = cinit_leg(P, torch, cat, voff, eoff, args.steps)
+    if not args.skip_adjoint and args.steps:
+        out["differentiation"] = adjoint_leg(P, torch)
     if not args.skip_ttt:
         F_star = reference_minimum()
         ttt = {"workload": "grid-1k", "F_star": F_star,
