@@ -350,3 +350,17 @@ def test_lds_residency_thresholds_bitwise(pgo):
                         assert h.info()["lds"] == 1
             assert np.array_equal(got["phase"], got["graph"]), (model, prec)
             assert np.isfinite(got["graph"]).all()
+
+
+@pytest.mark.parametrize("gamma", [1.0, 1.5, 1.9])
+def test_relaxation_steps_of_the_sphere_workload(pgo, gamma):
+    """The sphere workload at the relaxation steps its configuration sweeps
+    (gamma in {1.0, 1.5, 1.9}): FP64 and FP32 against the oracle after 10
+    sweeps."""
+    g = S.make_config("sphere-2.5k")
+    beta = 0.01 * abar(g)
+    _, st, _ = oracle_run(g, 10, beta, gamma)
+    ref = pack(st)
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        got, _, _ = gpu_run(pgo, g, 10, beta, gamma, precision=prec)
+        assert_parity(scaled_err(got, ref, beta), tol, f"sphere/{prec}/gamma={gamma}")
