@@ -218,7 +218,7 @@ DevAniso<T> viewa(const pgo_graph* g) {
 }
 
 // words of T per vertex of a rotation-like block (p, q, lambda and edge w)
-int rot_words(const pgo_graph* g) { return g->chordal ? 12 : 4; }
+int rot_words(const pgo_graph* g) { return g->chordal ? 9 : 4; }
 int state_width(const pgo_graph* g) { return g->chordal ? 36 : 21; }
 
 bool finite_all(const double* a, size_t k) {
@@ -787,7 +787,7 @@ pgo_status restore_flagged(pgo_graph* g, const std::vector<int32_t>& flags) {
   int words[6];
   for (int k = 0; k < 6; ++k) {
     src[k] = g->snap[k];
-    words[k] = int(vb[k] / 8);
+    words[k] = int(vb[k] / 4);
   }
   HIPCHK(launch_restore_words(int32_t(g->n), g->gid, g->flag_dev, dst, src, words, g->stream));
   HIPCHK(hipStreamSynchronize(g->stream));  // flags live on the host stack

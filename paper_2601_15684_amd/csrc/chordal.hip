@@ -48,7 +48,7 @@ template <typename A, typename T>
 __device__ __forceinline__ void ld9(const R3<T>& m, A out[9]) {
 #pragma unroll
   for (int r = 0; r < 3; ++r) {
-    const P4<T> row = m.r[r];
+    const V3<T> row = m.r[r];
     out[3 * r] = A(row.x);
     out[3 * r + 1] = A(row.y);
     out[3 * r + 2] = A(row.z);
@@ -59,7 +59,7 @@ template <typename T, typename A>
 __device__ __forceinline__ R3<T> st9(const A m[9]) {
   R3<T> o;
 #pragma unroll
-  for (int r = 0; r < 3; ++r) o.r[r] = P4<T>{T(m[3 * r]), T(m[3 * r + 1]), T(m[3 * r + 2]), T(0)};
+  for (int r = 0; r < 3; ++r) o.r[r] = V3<T>{T(m[3 * r]), T(m[3 * r + 1]), T(m[3 * r + 2])};
   return o;
 }
 
@@ -388,10 +388,14 @@ __global__ void k_phase_c(DevChordal<T> g, SweepParams sp, int save) {
 // neighbours (s in T; P in Q and T), t and Q likewise with fewer reads, z and
 // Lambda only by their owner.  A graph keeps the first kArrays of
 // s, P, t, Q, z, Lambda whose slots fit.
+// Each array starts on a 16-byte boundary (the padded 3-vectors are read as
+// aligned 16/32-byte words).
+__device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
+
 template <typename T>
-__device__ __forceinline__ size_t lds_prefix_c(int k) {
-  // bytes per vertex of the first k arrays of s, P, t, Q, z, Lambda
-  const size_t v = sizeof(P4<T>), r = sizeof(R3<T>);
+__device__ __forceinline__ size_t lds_prefix_c(int k, size_t n) {
+  // LDS bytes of the first k arrays of s, P, t, Q, z, Lambda for n vertices
+  const size_t v = align16(sizeof(P4<T>) * n), r = align16(sizeof(R3<T>) * n);
   const size_t c[7] = {0, v, v + r, 2 * v + r, 2 * v + 2 * r, 3 * v + 2 * r, 3 * v + 3 * r};
   return c[k];
 }
@@ -402,11 +406,12 @@ __device__ __forceinline__ void graph_sweeps_c(const DevChordal<T>& g, int v0, i
   const int n = v1 - v0;
   StateC<T> st = global_state(g);
   unsigned char* at = lds;
-  if (kArrays >= 1) st.s_ = reinterpret_cast<P4<T>*>(at), st.sb = v0, at += sizeof(P4<T>) * n;
-  if (kArrays >= 2) st.P_ = reinterpret_cast<R3<T>*>(at), st.Pb = v0, at += sizeof(R3<T>) * n;
-  if (kArrays >= 3) st.t_ = reinterpret_cast<P4<T>*>(at), st.tb = v0, at += sizeof(P4<T>) * n;
-  if (kArrays >= 4) st.Q_ = reinterpret_cast<R3<T>*>(at), st.Qb = v0, at += sizeof(R3<T>) * n;
-  if (kArrays >= 5) st.z_ = reinterpret_cast<P4<T>*>(at), st.zb = v0, at += sizeof(P4<T>) * n;
+  const size_t vb = align16(sizeof(P4<T>) * n), rb = align16(sizeof(R3<T>) * n);
+  if (kArrays >= 1) st.s_ = reinterpret_cast<P4<T>*>(at), st.sb = v0, at += vb;
+  if (kArrays >= 2) st.P_ = reinterpret_cast<R3<T>*>(at), st.Pb = v0, at += rb;
+  if (kArrays >= 3) st.t_ = reinterpret_cast<P4<T>*>(at), st.tb = v0, at += vb;
+  if (kArrays >= 4) st.Q_ = reinterpret_cast<R3<T>*>(at), st.Qb = v0, at += rb;
+  if (kArrays >= 5) st.z_ = reinterpret_cast<P4<T>*>(at), st.zb = v0, at += vb;
   if (kArrays >= 6) st.L_ = reinterpret_cast<R3<T>*>(at), st.Lb = v0;
   if (kArrays >= 1) {
     for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
@@ -457,7 +462,7 @@ __global__ void k_graph_sweeps_c(DevChordal<T> g, const int32_t* __restrict__ vo
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
   const size_t n = size_t(v1 - v0);
   int arrays = 0;
-  while (arrays < 6 && lds_prefix_c<T>(arrays + 1) * n <= size_t(lds_bytes)) ++arrays;
+  while (arrays < 6 && lds_prefix_c<T>(arrays + 1, n) <= size_t(lds_bytes)) ++arrays;
   switch (arrays) {
     case 6: graph_sweeps_c<6, T>(g, v0, v1, k, sp, lds_raw); break;
     case 5: graph_sweeps_c<5, T>(g, v0, v1, k, sp, lds_raw); break;
@@ -539,8 +544,8 @@ __global__ void k_init_state_c(DevChordal<T> g, const double* __restrict__ P0,
   if (i >= g.n) return;
   const R3<T> P = st9<T, double>(P0 + 9 * int64_t(i));
   const P4<T> t = P4<T>{T(t0[3 * i]), T(t0[3 * i + 1]), T(t0[3 * i + 2]), T(0)};
-  const R3<T> Z = {{P4<T>{T(0), T(0), T(0), T(0)}, P4<T>{T(0), T(0), T(0), T(0)},
-                    P4<T>{T(0), T(0), T(0), T(0)}}};
+  const R3<T> Z = {{V3<T>{T(0), T(0), T(0)}, V3<T>{T(0), T(0), T(0)},
+                    V3<T>{T(0), T(0), T(0)}}};
   const P4<T> z3 = P4<T>{T(0), T(0), T(0), T(0)};
   g.P[i] = P;
   g.Q[i] = P;
@@ -633,7 +638,7 @@ hipError_t launch_graph_sweeps_c(const DevChordal<T>& g, const int32_t* voff, co
   // enough for all six arrays of the largest graph, within the 160 KiB of a CU
   constexpr size_t kLds = 160 * 1024;
   const size_t all = 3 * (sizeof(P4<T>) + sizeof(R3<T>));
-  size_t bytes = lds ? std::min(kLds, all * size_t(max_n)) : 0;
+  size_t bytes = lds ? std::min(kLds, all * size_t(max_n) + 6 * 16) : 0;  // + alignment slack
   if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_c<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    int(bytes)) != hipSuccess) {

@@ -176,7 +176,7 @@ hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const 
                                hipStream_t st);
 
 // Boundary preparation and state transfer (prep.hip), FP64.
-// Device-to-device copy as a kernel (8-byte aligned, size a multiple of 8).
+// Device-to-device copy as a kernel (4-byte aligned, size a multiple of 4).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 // Projection onto SO(3) and conversion to a unit quaternion; bad[i] = 1
 // where rotation i fails det > 0 or ||R^T R - I||_F <= 1e-2.
@@ -273,7 +273,7 @@ template <typename T>
 hipError_t launch_poses_c(const DevChordal<T>& g, double* R, double* t, hipStream_t st);
 
 // Restores the six state arrays of every vertex whose graph is flagged;
-// words[k] = 8-byte words per vertex of array k.
+// words[k] = 4-byte words per vertex of array k (at most 32).
 hipError_t launch_restore_words(int32_t n, const int32_t* gid, const int32_t* flag,
                                 void* const* dst, const void* const* src, const int* words,
                                 hipStream_t st);

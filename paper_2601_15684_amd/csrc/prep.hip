@@ -318,8 +318,8 @@ PGO_INST(double)
 // Device-to-device copy of 8-byte words as an ordinary kernel on the stream,
 // so it is ordered with the sweep launches (plain or replayed graphs) exactly
 // like every other kernel of the library.
-__global__ void k_copy_words(uint64_t* __restrict__ dst, const uint64_t* __restrict__ src,
-                             int64_t words) {
+template <typename W>
+__global__ void k_copy_words(W* __restrict__ dst, const W* __restrict__ src, int64_t words) {
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   for (int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; k < words; k += stride)
     dst[k] = src[k];
@@ -327,18 +327,25 @@ __global__ void k_copy_words(uint64_t* __restrict__ dst, const uint64_t* __restr
 
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
-  if (bytes % 8 || reinterpret_cast<uintptr_t>(dst) % 8 || reinterpret_cast<uintptr_t>(src) % 8)
-    return hipErrorInvalidValue;
-  const int64_t words = int64_t(bytes / 8);
-  const int64_t blocks = std::min<int64_t>((words + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_copy_words, dim3(unsigned(blocks)), dim3(256), 0, st,
-                     static_cast<uint64_t*>(dst), static_cast<const uint64_t*>(src), words);
+  const uintptr_t a = reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src);
+  if (bytes % 4 || a % 4) return hipErrorInvalidValue;
+  if (bytes % 8 == 0 && a % 8 == 0) {
+    const int64_t words = int64_t(bytes / 8);
+    const int64_t blocks = std::min<int64_t>((words + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy_words<uint64_t>, dim3(unsigned(blocks)), dim3(256), 0, st,
+                       static_cast<uint64_t*>(dst), static_cast<const uint64_t*>(src), words);
+  } else {
+    const int64_t words = int64_t(bytes / 4);
+    const int64_t blocks = std::min<int64_t>((words + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_copy_words<uint32_t>, dim3(unsigned(blocks)), dim3(256), 0, st,
+                       static_cast<uint32_t*>(dst), static_cast<const uint32_t*>(src), words);
+  }
   return hipGetLastError();
 }
 
 struct RestoreArgs {
-  uint64_t* dst[6];
-  const uint64_t* src[6];
+  uint32_t* dst[6];
+  const uint32_t* src[6];
   int words[6];
 };
 
@@ -358,9 +365,9 @@ hipError_t launch_restore_words(int32_t n, const int32_t* gid, const int32_t* fl
   if (n <= 0) return hipSuccess;
   RestoreArgs a;
   for (int k = 0; k < 6; ++k) {
-    if (words[k] < 0 || words[k] > 16) return hipErrorInvalidValue;
-    a.dst[k] = static_cast<uint64_t*>(dst[k]);
-    a.src[k] = static_cast<const uint64_t*>(src[k]);
+    if (words[k] < 0 || words[k] > 32) return hipErrorInvalidValue;
+    a.dst[k] = static_cast<uint32_t*>(dst[k]);
+    a.src[k] = static_cast<const uint32_t*>(src[k]);
     a.words[k] = words[k];
   }
   hipLaunchKernelGGL(k_restore_words, dim3((n + 255) / 256), dim3(256), 0, st, n, gid, flag, a);

@@ -25,11 +25,11 @@ struct V3 {
   T x, y, z;
 };
 
-// 3x3 matrix as three padded rows (row r = (m[r][0], m[r][1], m[r][2], 0)),
-// so a row is one aligned 16/32-byte access.
+// 3x3 matrix as three packed rows, 9 words (row r = (m[r][0], m[r][1],
+// m[r][2])): a quarter fewer bytes to move than padded rows.
 template <typename T>
 struct R3 {
-  P4<T> r[3];
+  V3<T> r[3];
 };
 
 template <typename T>

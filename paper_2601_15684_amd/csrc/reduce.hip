@@ -109,8 +109,8 @@ __device__ __forceinline__ double dotq(const Q4<T>& l, const Q4<T>& a, const Q4<
          double(l.y) * (double(a.y) - double(b.y)) + double(l.z) * (double(a.z) - double(b.z));
 }
 
-template <typename T>
-__device__ __forceinline__ double dot3(const P4<T>& l, const P4<T>& a, const P4<T>& b) {
+template <typename V>
+__device__ __forceinline__ double dot3(const V& l, const V& a, const V& b) {
   return double(l.x) * (double(a.x) - double(b.x)) + double(l.y) * (double(a.y) - double(b.y)) +
          double(l.z) * (double(a.z) - double(b.z));
 }
@@ -214,7 +214,7 @@ __global__ void __launch_bounds__(kRB) k_red_edges_c(DevChordal<T> g, EdgeF64 E,
 template <typename T>
 __device__ __forceinline__ double d2m(const R3<T>& a, const R3<T>& b) {
   double s = 0.0;
-  for (int r = 0; r < 3; ++r) s += d2<T, P4<T>>(a.r[r], b.r[r]);
+  for (int r = 0; r < 3; ++r) s += d2<T, V3<T>>(a.r[r], b.r[r]);
   return s;
 }
 
