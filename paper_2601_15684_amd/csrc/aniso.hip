@@ -371,7 +371,7 @@ __device__ __forceinline__ Q4<T> qmul_pure_r(const Q4<T>& a, const V3<T>& b) {  
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
-                             const SweepParams& sp, const Q4<T>& qi_, const P4<T>& si_,
+                             const SweepParams& sp, const Q4<T>& qi_, const V3<T>& si_,
                              const Q4<T>& pi_, const Q4<T>& li_) {
   const DevGraph<T>& g = a.g;
   using A = double;  // the sphere-constrained solve is conditioned by A1's spectrum
@@ -381,7 +381,9 @@ __device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
   A bv[4] = {0, 0, 0, 0};
   A diag = A(sp.beta) + A(sp.h1);
   struct OutE {
-    P4<T> tt, tj, Sa, Sb;
+    P4<T> tt;
+    V3<T> tj;
+    P4<T> Sa, Sb;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1],
@@ -426,13 +428,15 @@ __device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, const State<T>& s
                                          const SweepParams& sp, bool save) {
   const DevGraph<T>& g = a.g;
   const Q4<T> pi = st.p(i), qi = st.q(i), li = st.lam(i);
-  const V3<T> si = v3(st.s(i));
+  const V3<T> si = st.s(i);
   const Q4<T> pic = qconj(pi);
   T M[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   T bv[4] = {0, 0, 0, 0};
   T diag = T(sp.beta) + T(sp.h2);
   struct OutE {
-    P4<T> tt, tj, Sa, Sb;
+    P4<T> tt;
+    V3<T> tj;
+    P4<T> Sa, Sb;
     Q4<T> pj, w;
   };
   edge_loop(
@@ -479,7 +483,9 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
   const DevGraph<T>& g = a.g;
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
-    P4<T> tt, sl, Sa, Sb;
+    P4<T> tt;
+    V3<T> sl;
+    P4<T> Sa, Sb;
     Q4<T> ql, pl;
   };
   edge_loop(
@@ -494,25 +500,27 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
             smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.sl.x + c.x, d.sl.y + c.y, d.sl.z + c.z});
         acc.x += y.x; acc.y += y.y; acc.z += y.z;
       });
-  const P4<T> ti = st.t(i), si = st.s(i);
-  const V3<T> zi = v3(st.z(i));
+  const V3<T> ti = st.t(i), si = st.s(i);
+  const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h3);
   const V3<T> rhs = {T(2) * acc.x + b * si.x + zi.x + h * ti.x, T(2) * acc.y + b * si.y + zi.y + h * ti.y,
                      T(2) * acc.z + b * si.z + zi.z + h * ti.z};
   if (save) g.t_prev[i] = ti;
-  st.t(i) = pad3(sym_solve3(sym3<T>(a.cTa[i], a.cTb[i]), b + h, rhs));
+  st.t(i) = sym_solve3(sym3<T>(a.cTa[i], a.cTb[i]), b + h, rhs);
 }
 
 template <typename T>
 __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& st, int i,
                                          const SweepParams& sp, bool save,
                                          Q4<T>* p_out = nullptr, Q4<T>* q_out = nullptr,
-                                         P4<T>* s_out = nullptr) {
+                                         V3<T>* s_out = nullptr) {
   const DevGraph<T>& g = a.g;
   const Q4<T> pi = st.p(i), qi = st.q(i);
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
-    P4<T> tt, tj, Sa, Sb;
+    P4<T> tt;
+    V3<T> tj;
+    P4<T> Sa, Sb;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1],
@@ -523,8 +531,8 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& s
             smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.tj.x - c.x, d.tj.y - c.y, d.tj.z - c.z});
         acc.x += y.x; acc.y += y.y; acc.z += y.z;
       });
-  const P4<T> ti = st.t(i), si = st.s(i);
-  const V3<T> zi = v3(st.z(i));
+  const V3<T> ti = st.t(i), si = st.s(i);
+  const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h4);
   const V3<T> rhs = {T(2) * acc.x + b * ti.x - zi.x + h * si.x, T(2) * acc.y + b * ti.y - zi.y + h * si.y,
                      T(2) * acc.z + b * ti.z - zi.z + h * si.z};
@@ -532,15 +540,15 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& s
   const T gb = T(sp.gamma * sp.beta);
   if (save) {
     g.s_prev[i] = si;
-    g.z_prev[i] = pad3(zi);
+    g.z_prev[i] = zi;
   }
-  st.s(i) = pad3(sn);
-  st.z(i) = pad3(V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
+  st.s(i) = sn;
+  st.z(i) = (V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
                        zi.z - gb * (ti.z - sn.z)});
   if (p_out) {
     *p_out = pi;
     *q_out = qi;
-    *s_out = pad3(sn);
+    *s_out = sn;
   }
 }
 
@@ -553,7 +561,7 @@ __device__ __forceinline__ void phase_a(const DevAniso<T>& a, const State<T>& st
   if (PH == 3) vertex_S(a, st, i, sp, save);
   if (PH == 4) {  // S of this sweep + P of the next
     Q4<T> pi, qi;
-    P4<T> si;
+    V3<T> si;
     vertex_S(a, st, i, sp, false, &pi, &qi, &si);
     vertex_P_own(a, st, i, sp, qi, si, pi, st.lam(i));
   }
@@ -620,8 +628,9 @@ __global__ void __launch_bounds__(kMaxBlockGraphA) k_graph_sweeps_a(
   const int v0 = voff[gr], v1 = voff[gr + 1];
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
-  const size_t per = size_t(v1 - v0) * sizeof(Q4<T>);
-  const int slots = int(std::min<size_t>(6, size_t(lds_bytes) / per));
+  const size_t n = size_t(v1 - v0);
+  int slots = 0;
+  while (slots < 6 && state_lds_bytes<T>(slots + 1, n) <= size_t(lds_bytes)) ++slots;
   switch (slots) {
     case 6: graph_sweeps_a<6, T>(a, v0, v1, k, sp, lds_raw); break;
     case 5: graph_sweeps_a<5, T>(a, v0, v1, k, sp, lds_raw); break;
@@ -704,7 +713,7 @@ hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, cons
   if (block <= 0 || block > kMaxBlockGraphA || block % 64) return hipErrorInvalidValue;
   // all six arrays of the largest graph, within the 160 KiB of a CU
   constexpr size_t kLds = 160 * 1024;
-  size_t bytes = lds ? std::min(kLds, 6 * sizeof(Q4<T>) * size_t(max_n)) : 0;
+  size_t bytes = lds ? std::min(kLds, state_lds_bytes<T>(6, size_t(max_n))) : 0;
   if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_a<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    int(bytes)) != hipSuccess) {

@@ -162,14 +162,14 @@ DevGraph<T> view(const pgo_graph* g) {
   d.p = static_cast<Q4<T>*>(g->p);
   d.q = static_cast<Q4<T>*>(g->q);
   d.lam = static_cast<Q4<T>*>(g->lam);
-  d.t = static_cast<P4<T>*>(g->t);
-  d.s = static_cast<P4<T>*>(g->s);
-  d.z = static_cast<P4<T>*>(g->z);
+  d.t = static_cast<V3<T>*>(g->t);
+  d.s = static_cast<V3<T>*>(g->s);
+  d.z = static_cast<V3<T>*>(g->z);
   d.q_prev = static_cast<Q4<T>*>(g->q_prev);
   d.lam_prev = static_cast<Q4<T>*>(g->lam_prev);
-  d.t_prev = static_cast<P4<T>*>(g->t_prev);
-  d.s_prev = static_cast<P4<T>*>(g->s_prev);
-  d.z_prev = static_cast<P4<T>*>(g->z_prev);
+  d.t_prev = static_cast<V3<T>*>(g->t_prev);
+  d.s_prev = static_cast<V3<T>*>(g->s_prev);
+  d.z_prev = static_cast<V3<T>*>(g->z_prev);
   return d;
 }
 
@@ -192,14 +192,14 @@ DevChordal<T> viewc(const pgo_graph* g) {
   d.P = static_cast<R3<T>*>(g->p);
   d.Q = static_cast<R3<T>*>(g->q);
   d.L = static_cast<R3<T>*>(g->lam);
-  d.t = static_cast<P4<T>*>(g->t);
-  d.s = static_cast<P4<T>*>(g->s);
-  d.z = static_cast<P4<T>*>(g->z);
+  d.t = static_cast<V3<T>*>(g->t);
+  d.s = static_cast<V3<T>*>(g->s);
+  d.z = static_cast<V3<T>*>(g->z);
   d.Q_prev = static_cast<R3<T>*>(g->q_prev);
   d.L_prev = static_cast<R3<T>*>(g->lam_prev);
-  d.t_prev = static_cast<P4<T>*>(g->t_prev);
-  d.s_prev = static_cast<P4<T>*>(g->s_prev);
-  d.z_prev = static_cast<P4<T>*>(g->z_prev);
+  d.t_prev = static_cast<V3<T>*>(g->t_prev);
+  d.s_prev = static_cast<V3<T>*>(g->s_prev);
+  d.z_prev = static_cast<V3<T>*>(g->z_prev);
   return d;
 }
 
@@ -320,9 +320,9 @@ pgo_status alloc_precision(pgo_graph* g) {
   void** rot[] = {&g->p, &g->q, &g->lam, &g->q_prev, &g->lam_prev};
   for (void** v : rot)
     if ((s = dalloc_bytes(g, v, rw * sizeof(T) * n)) != PGO_OK) return s;
-  void** vec4[] = {&g->t, &g->s, &g->z, &g->t_prev, &g->s_prev, &g->z_prev};
-  for (void** v : vec4)
-    if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * n)) != PGO_OK) return s;
+  void** vec3[] = {&g->t, &g->s, &g->z, &g->t_prev, &g->s_prev, &g->z_prev};
+  for (void** v : vec3)
+    if ((s = dalloc_bytes(g, v, 3 * sizeof(T) * n)) != PGO_OK) return s;
   void** e4[] = {&g->o_tt, &g->i_tt};
   for (void** v : e4)
     if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * m)) != PGO_OK) return s;
@@ -759,7 +759,7 @@ void merit_of(const double* v, double beta, double gamma, double* L, double* psi
 void state_array_bytes(const pgo_graph* g, size_t out[6]) {
   const size_t w = g->opt.precision == PGO_FP64 ? 8 : 4;
   for (int k = 0; k < 3; ++k) out[k] = size_t(rot_words(g)) * w;
-  for (int k = 3; k < 6; ++k) out[k] = 4 * w;
+  for (int k = 3; k < 6; ++k) out[k] = 3 * w;
 }
 
 pgo_status snapshot(pgo_graph* g) {
@@ -819,16 +819,18 @@ void** state_ptrs(pgo_graph* g, void** out6) {
 }
 
 pgo_status copy_state(pgo_graph* g, void* const* dst, void* const* src) {
+  size_t vb[6];
+  state_array_bytes(g, vb);
   for (int k = 0; k < 6; ++k)
-    HIPCHK(launch_copy(dst[k], src[k], state_bytes(g), g->stream));
+    HIPCHK(launch_copy(dst[k], src[k], vb[k] * size_t(g->n), g->stream));
   return PGO_OK;
 }
 
 template <typename T>
 StateRef<T> stateref(void* const* s6) {
   return StateRef<T>{static_cast<const Q4<T>*>(s6[0]), static_cast<const Q4<T>*>(s6[1]),
-                     static_cast<const Q4<T>*>(s6[2]), static_cast<const P4<T>*>(s6[3]),
-                     static_cast<const P4<T>*>(s6[4]), static_cast<const P4<T>*>(s6[5])};
+                     static_cast<const Q4<T>*>(s6[2]), static_cast<const V3<T>*>(s6[3]),
+                     static_cast<const V3<T>*>(s6[4]), static_cast<const V3<T>*>(s6[5])};
 }
 
 template <typename T>

@@ -79,16 +79,16 @@ struct StateC {
   R3<T>* P_;
   R3<T>* Q_;
   R3<T>* L_;
-  P4<T>* t_;
-  P4<T>* s_;
-  P4<T>* z_;
+  V3<T>* t_;
+  V3<T>* s_;
+  V3<T>* z_;
   int Pb, Qb, Lb, tb, sb, zb;
   __device__ __forceinline__ R3<T>& P(int j) const { return P_[j - Pb]; }
   __device__ __forceinline__ R3<T>& Q(int j) const { return Q_[j - Qb]; }
   __device__ __forceinline__ R3<T>& L(int j) const { return L_[j - Lb]; }
-  __device__ __forceinline__ P4<T>& t(int j) const { return t_[j - tb]; }
-  __device__ __forceinline__ P4<T>& s(int j) const { return s_[j - sb]; }
-  __device__ __forceinline__ P4<T>& z(int j) const { return z_[j - zb]; }
+  __device__ __forceinline__ V3<T>& t(int j) const { return t_[j - tb]; }
+  __device__ __forceinline__ V3<T>& s(int j) const { return s_[j - sb]; }
+  __device__ __forceinline__ V3<T>& z(int j) const { return z_[j - zb]; }
 };
 
 template <typename T>
@@ -117,7 +117,7 @@ __device__ __forceinline__ void m_out_zero(MOut<A>& mo) {
 }
 
 template <typename A, bool kMag, typename T>
-__device__ __forceinline__ void m_out_add(MOut<A>& mo, const A ti[3], const P4<T>& tj,
+__device__ __forceinline__ void m_out_add(MOut<A>& mo, const A ti[3], const V3<T>& tj,
                                           const P4<T>& u) {
   const A d[3] = {A(tj.x) - ti[0], A(tj.y) - ti[1], A(tj.z) - ti[2]};
   const A uu[3] = {A(u.x), A(u.y), A(u.z)};
@@ -137,7 +137,7 @@ __device__ __forceinline__ void m_out_add(MOut<A>& mo, const A ti[3], const P4<T
 template <typename A, typename T, bool kMag>
 __device__ void p_matrix(const DevChordal<T>& g, const StateC<T>& st, int i, const SweepParams& sp,
                          const R3<T>& Qi_,
-                         const P4<T>& ti_, const P4<T>& si_, const R3<T>& Pi_, const R3<T>& Li_,
+                         const V3<T>& ti_, const V3<T>& si_, const R3<T>& Pi_, const R3<T>& Li_,
                          A M[9], A& mag, const MOut<A>* pre = nullptr) {
   const A ti[3] = {A(ti_.x), A(ti_.y), A(ti_.z)};
   MOut<A> mo;
@@ -146,7 +146,8 @@ __device__ void p_matrix(const DevChordal<T>& g, const StateC<T>& st, int i, con
   } else {
     m_out_zero(mo);
     struct OutE {
-      P4<T> tj, u;
+      V3<T> tj;
+      P4<T> u;
     };
     edge_loop(
         g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{st.t(g.o_nbr[e]), g.o_tt[e]}; },
@@ -202,8 +203,8 @@ __device__ __forceinline__ A polar_gap(const A M[9], const A sig[3]) {
 // phase has them in registers).  P_i is kept when M_i = 0.
 template <typename T>
 __device__ void vertex_P_own(const DevChordal<T>& g, const StateC<T>& st, int i,
-                             const SweepParams& sp, const R3<T>& Qi, const P4<T>& ti,
-                             const P4<T>& si, const R3<T>& Pi, const R3<T>& Li,
+                             const SweepParams& sp, const R3<T>& Qi, const V3<T>& ti,
+                             const V3<T>& si, const R3<T>& Pi, const R3<T>& Li,
                              const MOut<T>* pre = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   T M[9], R[9], sig[3], mag = T(0);
@@ -274,7 +275,8 @@ __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, const StateC<T>
                                          const SweepParams& sp, bool save) {
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
-    P4<T> u, sl;
+    P4<T> u;
+    V3<T> sl;
     R3<T> Pl;
   };
   edge_loop(
@@ -289,29 +291,30 @@ __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, const StateC<T>
         acc.y += x.u.u * x.sl.y + c.y;
         acc.z += x.u.u * x.sl.z + c.z;
       });
-  const P4<T> ti = st.t(i), si = st.s(i);
-  const V3<T> zi = v3(st.z(i));
+  const V3<T> ti = st.t(i), si = st.s(i);
+  const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h3);
   const T a = g.cT[i] + b + h;
   if (save) g.t_prev[i] = ti;
-  st.t(i) = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+  st.t(i) = V3<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
                   (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
-                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
+                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a};
 }
 
 template <typename T>
 __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, const StateC<T>& st, int i,
                                          const SweepParams& sp, bool save,
                                          R3<T>* P_out = nullptr, R3<T>* Q_out = nullptr,
-                                         P4<T>* t_out = nullptr, P4<T>* s_out = nullptr,
+                                         V3<T>* t_out = nullptr, V3<T>* s_out = nullptr,
                                          MOut<T>* mo = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   const R3<T> Pi = st.P(i);
-  const P4<T> ti = st.t(i), si = st.s(i);
+  const V3<T> ti = st.t(i), si = st.s(i);
   const T tiv[3] = {ti.x, ti.y, ti.z};
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
-    P4<T> u, tj;
+    P4<T> u;
+    V3<T> tj;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e])}; },
@@ -322,7 +325,7 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, const StateC<T>
         acc.z += x.u.u * x.tj.z - c.z;
         if (mo) m_out_add<T, kF32>(*mo, tiv, x.tj, x.u);  // the next P's out-edge sum
       });
-  const V3<T> zi = v3(st.z(i));
+  const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h4);
   const T a = g.cS[i] + b + h;
   const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
@@ -331,16 +334,15 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, const StateC<T>
   const T gb = T(sp.gamma * sp.beta);
   if (save) {
     g.s_prev[i] = si;
-    g.z_prev[i] = pad3(zi);
+    g.z_prev[i] = zi;
   }
-  st.s(i) = pad3(sn);
-  st.z(i) = pad3(V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
-                       zi.z - gb * (ti.z - sn.z)});
+  st.s(i) = sn;
+  st.z(i) = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
   if (P_out) {
     *P_out = Pi;
     *Q_out = st.Q(i);
     *t_out = ti;
-    *s_out = pad3(sn);
+    *s_out = sn;
   }
 }
 
@@ -353,7 +355,7 @@ __device__ __forceinline__ void phase_c(const DevChordal<T>& g, const StateC<T>&
   if (PH == 3) vertex_S(g, st, i, sp, save);
   if (PH == 4) {  // S of this sweep + P of the next
     R3<T> Pi, Qi;
-    P4<T> ti, si;
+    V3<T> ti, si;
     MOut<T> mo;
     m_out_zero(mo);
     vertex_S(g, st, i, sp, false, &Pi, &Qi, &ti, &si, &mo);
@@ -395,7 +397,7 @@ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(
 template <typename T>
 __device__ __forceinline__ size_t lds_prefix_c(int k, size_t n) {
   // LDS bytes of the first k arrays of s, P, t, Q, z, Lambda for n vertices
-  const size_t v = align16(sizeof(P4<T>) * n), r = align16(sizeof(R3<T>) * n);
+  const size_t v = align16(sizeof(V3<T>) * n), r = align16(sizeof(R3<T>) * n);
   const size_t c[7] = {0, v, v + r, 2 * v + r, 2 * v + 2 * r, 3 * v + 2 * r, 3 * v + 3 * r};
   return c[k];
 }
@@ -406,12 +408,12 @@ __device__ __forceinline__ void graph_sweeps_c(const DevChordal<T>& g, int v0, i
   const int n = v1 - v0;
   StateC<T> st = global_state(g);
   unsigned char* at = lds;
-  const size_t vb = align16(sizeof(P4<T>) * n), rb = align16(sizeof(R3<T>) * n);
-  if (kArrays >= 1) st.s_ = reinterpret_cast<P4<T>*>(at), st.sb = v0, at += vb;
+  const size_t vb = align16(sizeof(V3<T>) * n), rb = align16(sizeof(R3<T>) * n);
+  if (kArrays >= 1) st.s_ = reinterpret_cast<V3<T>*>(at), st.sb = v0, at += vb;
   if (kArrays >= 2) st.P_ = reinterpret_cast<R3<T>*>(at), st.Pb = v0, at += rb;
-  if (kArrays >= 3) st.t_ = reinterpret_cast<P4<T>*>(at), st.tb = v0, at += vb;
+  if (kArrays >= 3) st.t_ = reinterpret_cast<V3<T>*>(at), st.tb = v0, at += vb;
   if (kArrays >= 4) st.Q_ = reinterpret_cast<R3<T>*>(at), st.Qb = v0, at += rb;
-  if (kArrays >= 5) st.z_ = reinterpret_cast<P4<T>*>(at), st.zb = v0, at += vb;
+  if (kArrays >= 5) st.z_ = reinterpret_cast<V3<T>*>(at), st.zb = v0, at += vb;
   if (kArrays >= 6) st.L_ = reinterpret_cast<R3<T>*>(at), st.Lb = v0;
   if (kArrays >= 1) {
     for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) {
@@ -543,10 +545,10 @@ __global__ void k_init_state_c(DevChordal<T> g, const double* __restrict__ P0,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
   const R3<T> P = st9<T, double>(P0 + 9 * int64_t(i));
-  const P4<T> t = P4<T>{T(t0[3 * i]), T(t0[3 * i + 1]), T(t0[3 * i + 2]), T(0)};
+  const V3<T> t = V3<T>{T(t0[3 * i]), T(t0[3 * i + 1]), T(t0[3 * i + 2])};
   const R3<T> Z = {{V3<T>{T(0), T(0), T(0)}, V3<T>{T(0), T(0), T(0)},
                     V3<T>{T(0), T(0), T(0)}}};
-  const P4<T> z3 = P4<T>{T(0), T(0), T(0), T(0)};
+  const V3<T> z3 = V3<T>{T(0), T(0), T(0)};
   g.P[i] = P;
   g.Q[i] = P;
   g.L[i] = Z;
@@ -568,17 +570,17 @@ __global__ void k_state_io_c(DevChordal<T> g, double* __restrict__ buf, int to_d
   if (to_device) {
     g.P[i] = st9<T, double>(b);
     g.Q[i] = st9<T, double>(b + 9);
-    g.t[i] = P4<T>{T(b[18]), T(b[19]), T(b[20]), T(0)};
-    g.s[i] = P4<T>{T(b[21]), T(b[22]), T(b[23]), T(0)};
+    g.t[i] = V3<T>{T(b[18]), T(b[19]), T(b[20])};
+    g.s[i] = V3<T>{T(b[21]), T(b[22]), T(b[23])};
     g.L[i] = st9<T, double>(b + 24);
-    g.z[i] = P4<T>{T(b[33]), T(b[34]), T(b[35]), T(0)};
+    g.z[i] = V3<T>{T(b[33]), T(b[34]), T(b[35])};
   } else {
     double v[9];
     ld9<double>(g.P[i], v);
     for (int k = 0; k < 9; ++k) b[k] = v[k];
     ld9<double>(g.Q[i], v);
     for (int k = 0; k < 9; ++k) b[9 + k] = v[k];
-    const P4<T> t = g.t[i], s = g.s[i], z = g.z[i];
+    const V3<T> t = g.t[i], s = g.s[i], z = g.z[i];
     b[18] = double(t.x); b[19] = double(t.y); b[20] = double(t.z);
     b[21] = double(s.x); b[22] = double(s.y); b[23] = double(s.z);
     ld9<double>(g.L[i], v);
@@ -597,7 +599,7 @@ __global__ void k_poses_c(DevChordal<T> g, double* __restrict__ R, double* __res
     for (int k = 0; k < 9; ++k) R[9 * int64_t(i) + k] = v[k];
   }
   if (t) {
-    const P4<T> x = g.t[i];
+    const V3<T> x = g.t[i];
     t[3 * int64_t(i)] = double(x.x);
     t[3 * int64_t(i) + 1] = double(x.y);
     t[3 * int64_t(i) + 2] = double(x.z);
@@ -637,7 +639,7 @@ hipError_t launch_graph_sweeps_c(const DevChordal<T>& g, const int32_t* voff, co
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
   // enough for all six arrays of the largest graph, within the 160 KiB of a CU
   constexpr size_t kLds = 160 * 1024;
-  const size_t all = 3 * (sizeof(P4<T>) + sizeof(R3<T>));
+  const size_t all = 3 * (sizeof(V3<T>) + sizeof(R3<T>));
   size_t bytes = lds ? std::min(kLds, all * size_t(max_n) + 6 * 16) : 0;  // + alignment slack
   if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_c<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,

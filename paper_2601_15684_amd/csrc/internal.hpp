@@ -39,15 +39,15 @@ struct DevGraph {
   Q4<T>* p;
   Q4<T>* q;
   Q4<T>* lam;
-  P4<T>* t;
-  P4<T>* s;
-  P4<T>* z;
+  V3<T>* t;
+  V3<T>* s;
+  V3<T>* z;
   // values before the last sweep of an iterate call (residual history)
   Q4<T>* q_prev;
   Q4<T>* lam_prev;
-  P4<T>* t_prev;
-  P4<T>* s_prev;
-  P4<T>* z_prev;
+  V3<T>* t_prev;
+  V3<T>* s_prev;
+  V3<T>* z_prev;
 };
 
 // Where the state of the vertices being updated lives during a sweep: each
@@ -58,17 +58,17 @@ template <typename T>
 struct State {
   Q4<T>* p_;
   Q4<T>* q_;
-  P4<T>* t_;
-  P4<T>* s_;
+  V3<T>* t_;
+  V3<T>* s_;
   Q4<T>* lam_;
-  P4<T>* z_;
+  V3<T>* z_;
   int pb, qb, tb, sb, lb, zb;
   __device__ __forceinline__ Q4<T>& p(int j) const { return p_[j - pb]; }
   __device__ __forceinline__ Q4<T>& q(int j) const { return q_[j - qb]; }
-  __device__ __forceinline__ P4<T>& t(int j) const { return t_[j - tb]; }
-  __device__ __forceinline__ P4<T>& s(int j) const { return s_[j - sb]; }
+  __device__ __forceinline__ V3<T>& t(int j) const { return t_[j - tb]; }
+  __device__ __forceinline__ V3<T>& s(int j) const { return s_[j - sb]; }
   __device__ __forceinline__ Q4<T>& lam(int j) const { return lam_[j - lb]; }
-  __device__ __forceinline__ P4<T>& z(int j) const { return z_[j - zb]; }
+  __device__ __forceinline__ V3<T>& z(int j) const { return z_[j - zb]; }
 };
 
 template <typename T>
@@ -76,24 +76,33 @@ __device__ __forceinline__ State<T> global_state(const DevGraph<T>& g) {
   return {g.p, g.q, g.t, g.s, g.lam, g.z, 0, 0, 0, 0, 0, 0};
 }
 
+// LDS bytes of the first k of p, q, t, s, lambda, z for n vertices, each
+// array starting on a 16-byte boundary.
+template <typename T>
+__host__ __device__ __forceinline__ size_t state_lds_bytes(int k, size_t n) {
+  const size_t q = (sizeof(Q4<T>) * n + 15) & ~size_t(15), v = (sizeof(V3<T>) * n + 15) & ~size_t(15);
+  const size_t c[7] = {0, q, 2 * q, 2 * q + v, 2 * q + 2 * v, 3 * q + 2 * v, 3 * q + 3 * v};
+  return c[k];
+}
+
 // Places the first k of p, q, t, s, lambda, z of the graph's vertices
-// [v0, v1) in LDS (k slots of sizeof(Q4<T>) per vertex from lds), loads
-// them, and returns the view; the caller runs its sweeps and hands the view
-// to state_store.  Every vertex's slots are written only by the thread that
+// [v0, v1) in LDS (laid out as state_lds_bytes counts them), loads them,
+// and returns the view; the caller runs its sweeps and hands the view to
+// state_store.  Every vertex's slots are written only by the thread that
 // owns the vertex, which also loads and stores them.
 template <int kSlots, typename T>
 __device__ __forceinline__ State<T> state_load(const DevGraph<T>& g, int v0, int v1,
                                                unsigned char* lds) {
-  const int n = v1 - v0;
+  const size_t n = size_t(v1 - v0);
   State<T> st = global_state(g);
-  Q4<T>* lq = reinterpret_cast<Q4<T>*>(lds);
-  P4<T>* lv = reinterpret_cast<P4<T>*>(lds);
-  if (kSlots >= 1) st.p_ = lq, st.pb = v0;
-  if (kSlots >= 2) st.q_ = lq + n, st.qb = v0;
-  if (kSlots >= 3) st.t_ = lv + 2 * n, st.tb = v0;
-  if (kSlots >= 4) st.s_ = lv + 3 * n, st.sb = v0;
-  if (kSlots >= 5) st.lam_ = lq + 4 * n, st.lb = v0;
-  if (kSlots >= 6) st.z_ = lv + 5 * n, st.zb = v0;
+  const size_t qb = state_lds_bytes<T>(1, n), vb = state_lds_bytes<T>(3, n) - 2 * qb;
+  unsigned char* at = lds;
+  if (kSlots >= 1) st.p_ = reinterpret_cast<Q4<T>*>(at), st.pb = v0, at += qb;
+  if (kSlots >= 2) st.q_ = reinterpret_cast<Q4<T>*>(at), st.qb = v0, at += qb;
+  if (kSlots >= 3) st.t_ = reinterpret_cast<V3<T>*>(at), st.tb = v0, at += vb;
+  if (kSlots >= 4) st.s_ = reinterpret_cast<V3<T>*>(at), st.sb = v0, at += vb;
+  if (kSlots >= 5) st.lam_ = reinterpret_cast<Q4<T>*>(at), st.lb = v0, at += qb;
+  if (kSlots >= 6) st.z_ = reinterpret_cast<V3<T>*>(at), st.zb = v0;
   if (kSlots >= 1) {
     for (int i = v0 + int(threadIdx.x); i < v1; i += int(blockDim.x)) {
       st.p(i) = g.p[i];
@@ -152,14 +161,14 @@ struct DevChordal {
   R3<T>* P;
   R3<T>* Q;
   R3<T>* L;
-  P4<T>* t;
-  P4<T>* s;
-  P4<T>* z;
+  V3<T>* t;
+  V3<T>* s;
+  V3<T>* z;
   R3<T>* Q_prev;
   R3<T>* L_prev;
-  P4<T>* t_prev;
-  P4<T>* s_prev;
-  P4<T>* z_prev;
+  V3<T>* t_prev;
+  V3<T>* s_prev;
+  V3<T>* z_prev;
 };
 
 // Launchers (sweep.hip).  Every launcher checks its own configuration and
@@ -394,9 +403,9 @@ struct StateRef {
   const Q4<T>* p;
   const Q4<T>* q;
   const Q4<T>* lam;
-  const P4<T>* t;
-  const P4<T>* s;
-  const P4<T>* z;
+  const V3<T>* t;
+  const V3<T>* s;
+  const V3<T>* z;
 };
 
 template <typename T>

@@ -148,9 +148,9 @@ __global__ void k_init_state(DevGraph<T> g, const Q4<double>* __restrict__ p0,
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n) return;
   const Q4<T> p = cvt<T>(p0[i]);
-  const P4<T> t = {T(t0[3 * int64_t(i)]), T(t0[3 * int64_t(i) + 1]), T(t0[3 * int64_t(i) + 2]), T(0)};
+  const V3<T> t = {T(t0[3 * int64_t(i)]), T(t0[3 * int64_t(i) + 1]), T(t0[3 * int64_t(i) + 2])};
   const Q4<T> zq = {T(0), T(0), T(0), T(0)};
-  const P4<T> zv = {T(0), T(0), T(0), T(0)};
+  const V3<T> zv = {T(0), T(0), T(0)};
   g.p[i] = p;
   g.q[i] = p;
   g.t[i] = t;
@@ -172,7 +172,7 @@ __global__ void k_state_io(DevGraph<T> g, double* __restrict__ buf, int to_devic
   double* b = buf + 21 * int64_t(i);
   if (!to_device) {
     const Q4<T> p = g.p[i], q = g.q[i], l = g.lam[i];
-    const P4<T> t = g.t[i], s = g.s[i], z = g.z[i];
+    const V3<T> t = g.t[i], s = g.s[i], z = g.z[i];
     const double v[21] = {double(p.w), double(p.x), double(p.y), double(p.z),
                           double(q.w), double(q.x), double(q.y), double(q.z),
                           double(t.x), double(t.y), double(t.z),
@@ -183,10 +183,10 @@ __global__ void k_state_io(DevGraph<T> g, double* __restrict__ buf, int to_devic
   } else {
     g.p[i] = Q4<T>{T(b[0]), T(b[1]), T(b[2]), T(b[3])};
     g.q[i] = Q4<T>{T(b[4]), T(b[5]), T(b[6]), T(b[7])};
-    g.t[i] = P4<T>{T(b[8]), T(b[9]), T(b[10]), T(0)};
-    g.s[i] = P4<T>{T(b[11]), T(b[12]), T(b[13]), T(0)};
+    g.t[i] = V3<T>{T(b[8]), T(b[9]), T(b[10])};
+    g.s[i] = V3<T>{T(b[11]), T(b[12]), T(b[13])};
     g.lam[i] = Q4<T>{T(b[14]), T(b[15]), T(b[16]), T(b[17])};
-    g.z[i] = P4<T>{T(b[18]), T(b[19]), T(b[20]), T(0)};
+    g.z[i] = V3<T>{T(b[18]), T(b[19]), T(b[20])};
     g.q_prev[i] = g.q[i];
     g.lam_prev[i] = g.lam[i];
     g.t_prev[i] = g.t[i];
@@ -211,7 +211,7 @@ __global__ void k_poses(DevGraph<T> g, double* __restrict__ R, double* __restric
     }
   }
   if (t) {
-    const P4<T> ti = g.t[i];
+    const V3<T> ti = g.t[i];
     t[3 * int64_t(i)] = double(ti.x);
     t[3 * int64_t(i) + 1] = double(ti.y);
     t[3 * int64_t(i) + 2] = double(ti.z);

@@ -83,6 +83,11 @@ __device__ __forceinline__ V3<T> v3(const P4<T>& a) {
 }
 
 template <typename T>
+__device__ __forceinline__ V3<T> v3(const V3<T>& a) {
+  return a;
+}
+
+template <typename T>
 __device__ __forceinline__ P4<T> pad3(const V3<T>& v, T u = T(0)) {
   return {v.x, v.y, v.z, u};
 }

@@ -40,7 +40,7 @@ template <typename T>
 __device__ double edge_cost(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
   const int i = E.ei[e], j = E.ej[e];
   const Q4<double> pi = cvt<double>(g.p[i]), pj = cvt<double>(g.p[j]);
-  const P4<T> ti = g.t[i], tj = g.t[j];
+  const V3<T> ti = g.t[i], tj = g.t[j];
   const V3<double> tt = {E.tm[3 * e], E.tm[3 * e + 1], E.tm[3 * e + 2]};
   const Q4<double> rot = qmul(qmul_vp(pi, tt), qconj(pi));  // p_i [0, t~] p_i^*
   const double r0 = -rot.w;
@@ -59,7 +59,7 @@ template <typename T>
 __device__ double edge_split(const DevGraph<T>& g, const EdgeF64& E, int64_t e) {
   const int i = E.ei[e], j = E.ej[e];
   const Q4<double> pi = cvt<double>(g.p[i]), qi = cvt<double>(g.q[i]), pj = cvt<double>(g.p[j]);
-  const P4<T> si = g.s[i], tj = g.t[j];
+  const V3<T> si = g.s[i], tj = g.t[j];
   const V3<double> tt = {E.tm[3 * e], E.tm[3 * e + 1], E.tm[3 * e + 2]};
   const Q4<double> rot = qmul(qmul_vp(qi, tt), qconj(pi));  // q_i [0, t~] p_i^*
   const double r0 = -rot.w;
@@ -125,15 +125,15 @@ __global__ void __launch_bounds__(kRB) k_red_vertices(DevGraph<T> g, int have_pr
   const int c = blockIdx.x;
   for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
     v[0] += d2q(g.p[i], g.q[i]);
-    v[1] += d2<T, P4<T>>(g.t[i], g.s[i]);
+    v[1] += d2<T, V3<T>>(g.t[i], g.s[i]);
     v[7] += dotq(g.lam[i], g.p[i], g.q[i]);
     v[8] += dot3(g.z[i], g.t[i], g.s[i]);
     if (have_prev) {
       v[2] += d2q(g.lam[i], g.lam_prev[i]);
-      v[3] += d2<T, P4<T>>(g.z[i], g.z_prev[i]);
+      v[3] += d2<T, V3<T>>(g.z[i], g.z_prev[i]);
       v[4] += d2q(g.q[i], g.q_prev[i]);
-      v[5] += d2<T, P4<T>>(g.t[i], g.t_prev[i]);
-      v[6] += d2<T, P4<T>>(g.s[i], g.s_prev[i]);
+      v[5] += d2<T, V3<T>>(g.t[i], g.t_prev[i]);
+      v[6] += d2<T, V3<T>>(g.s[i], g.s_prev[i]);
     }
   }
   block_sum<kVertVals>(v, sh);
@@ -170,7 +170,7 @@ __device__ __forceinline__ void rowsd(const R3<T>& m, double o[9]) {
 // (A, B, b) = (P, P, t), the split f + g with (A, B, b) = (P, Q, s).
 template <typename T>
 __device__ double edge_chordal(const EdgeF64& E, int64_t e, const R3<T>& Ai_, const R3<T>& Bi_,
-                               const R3<T>& Pj_, const P4<T>& bi, const P4<T>& tj) {
+                               const R3<T>& Pj_, const V3<T>& bi, const V3<T>& tj) {
   double A[9], B[9], Pj[9];
   rowsd(Ai_, A);
   rowsd(Bi_, B);
@@ -235,15 +235,15 @@ __global__ void __launch_bounds__(kRB) k_red_vertices_c(DevChordal<T> g, int hav
   const int c = blockIdx.x;
   for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
     v[0] += d2m(g.P[i], g.Q[i]);
-    v[1] += d2<T, P4<T>>(g.t[i], g.s[i]);
+    v[1] += d2<T, V3<T>>(g.t[i], g.s[i]);
     v[7] += dotm(g.L[i], g.P[i], g.Q[i]);
     v[8] += dot3(g.z[i], g.t[i], g.s[i]);
     if (have_prev) {
       v[2] += d2m(g.L[i], g.L_prev[i]);
-      v[3] += d2<T, P4<T>>(g.z[i], g.z_prev[i]);
+      v[3] += d2<T, V3<T>>(g.z[i], g.z_prev[i]);
       v[4] += d2m(g.Q[i], g.Q_prev[i]);
-      v[5] += d2<T, P4<T>>(g.t[i], g.t_prev[i]);
-      v[6] += d2<T, P4<T>>(g.s[i], g.s_prev[i]);
+      v[5] += d2<T, V3<T>>(g.t[i], g.t_prev[i]);
+      v[6] += d2<T, V3<T>>(g.s[i], g.s_prev[i]);
     }
   }
   block_sum<kVertVals>(v, sh);

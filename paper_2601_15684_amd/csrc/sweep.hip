@@ -41,8 +41,8 @@
 
 namespace pgo {
 
-template <typename A, typename T>
-__device__ __forceinline__ V3<A> v3a(const P4<T>& a) {
+template <typename A, typename V>
+__device__ __forceinline__ V3<A> v3a(const V& a) {  // first three components of P4 or V3
   return {A(a.x), A(a.y), A(a.z)};
 }
 
@@ -78,7 +78,7 @@ __device__ __forceinline__ POut<A> p_out_zero() {
 
 template <typename A, bool kMag, typename T>
 __device__ __forceinline__ void p_out_add(POut<A>& po, const Q4<A>& qi, const V3<A>& ti,
-                                          const P4<T>& tj_, const P4<T>& u_) {
+                                          const V3<T>& tj_, const P4<T>& u_) {
   const V3<A> tj = v3a<A>(tj_), u = v3a<A>(u_);
   const V3<A> d = {ti.x - tj.x, ti.y - tj.y, ti.z - tj.z};
   const Q4<A> term = qmul_vp(qmul_pv(d, qi), u);
@@ -102,7 +102,7 @@ __device__ __forceinline__ Q4<A> p_out_finish(const POut<A>& po, const Q4<A>& qi
 // out-edge part is taken from pre when the caller gathered it already.
 template <typename A, typename T, bool kMag>
 __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, const State<T>& st, int i,
-                                            const Q4<T>& q_i, const P4<T>& t_i, const P4<T>& s_i,
+                                            const Q4<T>& q_i, const V3<T>& t_i, const V3<T>& s_i,
                                             A& mag, const POut<A>* pre = nullptr) {
   const Q4<A> qi = cvt<A>(q_i);
   const V3<A> ti = v3a<A>(t_i);
@@ -112,7 +112,8 @@ __device__ __forceinline__ Q4<A> p_edge_sum(const DevGraph<T>& g, const State<T>
   } else {
     po = p_out_zero<A>();
     struct OutE {
-      P4<T> tj, u;
+      V3<T> tj;
+      P4<T> u;
     };
     edge_loop(
         g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{st.t(g.o_nbr[e]), g.o_tt[e]}; },
@@ -147,7 +148,7 @@ __device__ __forceinline__ Q4<A> p_vector(const Q4<A>& acc, const Q4<T>& q_i, co
 template <typename T>
 __device__ __forceinline__ void vertex_P_own(const DevGraph<T>& g, const State<T>& st, int i,
                                              const SweepParams& sp, const Q4<T>& qi,
-                                             const P4<T>& ti, const P4<T>& si, const Q4<T>& pi,
+                                             const V3<T>& ti, const V3<T>& si, const Q4<T>& pi,
                                              const Q4<T>& li, const POut<T>* pre = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   T mag = T(0);
@@ -180,10 +181,11 @@ template <typename T>
 __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const State<T>& st, int i,
                                          const SweepParams& sp, bool save) {
   const Q4<T> pi = st.p(i), qi = st.q(i), li = st.lam(i);
-  const V3<T> si = v3(st.s(i));
+  const V3<T> si = st.s(i);
   Q4<T> acc = {T(0), T(0), T(0), T(0)};
   struct OutE {
-    P4<T> tj, u;
+    V3<T> tj;
+    P4<T> u;
     Q4<T> pj, w;
   };
   edge_loop(
@@ -193,7 +195,7 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const State<T>& s
         return OutE{st.t(j), g.o_tt[e], st.p(j), g.o_w[e]};
       },
       [&](const OutE& d) {
-        const V3<T> tj = v3(d.tj);
+        const V3<T> tj = d.tj;
         const V3<T> r = {tj.x - si.x, tj.y - si.y, tj.z - si.z};
         const V3<T> mu = {-d.u.x, -d.u.y, -d.u.z};  // [0, tau t~]^*
         acc4(acc, qmul_vp(qmul_pv(r, pi), mu));
@@ -220,7 +222,8 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const State<T>& s
                                          const SweepParams& sp, bool save) {
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
-    P4<T> u, sl;
+    P4<T> u;
+    V3<T> sl;
     Q4<T> ql, pl;
   };
   edge_loop(
@@ -235,13 +238,13 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const State<T>& s
         acc.y += d.u.u * d.sl.y + c.y;
         acc.z += d.u.u * d.sl.z + c.z;
       });
-  const P4<T> ti = st.t(i), si = st.s(i), zi = st.z(i);
+  const V3<T> ti = st.t(i), si = st.s(i), zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h3);
   const T a = g.cT[i] + b + h;
   if (save) g.t_prev[i] = ti;
-  st.t(i) = P4<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+  st.t(i) = V3<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
                   (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
-                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a, T(0)};
+                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a};
 }
 
 // S update of vertex i; with po, the same pass over the out-edges also
@@ -251,15 +254,16 @@ template <typename T>
 __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, const State<T>& st, int i,
                                          const SweepParams& sp, bool save,
                                          POut<T>* po = nullptr, Q4<T>* p_out = nullptr,
-                                         Q4<T>* q_out = nullptr, P4<T>* t_out = nullptr,
-                                         P4<T>* s_out = nullptr) {
+                                         Q4<T>* q_out = nullptr, V3<T>* t_out = nullptr,
+                                         V3<T>* s_out = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   const Q4<T> pi = st.p(i), qi = st.q(i);
-  const P4<T> ti = st.t(i), si = st.s(i);
-  const V3<T> tiv = v3(ti);
+  const V3<T> ti = st.t(i), si = st.s(i);
+  const V3<T> tiv = ti;
   V3<T> acc = {T(0), T(0), T(0)};
   struct OutE {
-    P4<T> u, tj;
+    P4<T> u;
+    V3<T> tj;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e])}; },
@@ -270,7 +274,7 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, const State<T>& s
         acc.z += d.u.u * d.tj.z - c.z;
         if (po) p_out_add<T, kF32>(*po, qi, tiv, d.tj, d.u);  // the next P's out-edge sum
       });
-  const V3<T> zi = v3(st.z(i));
+  const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h4);
   const T a = g.cS[i] + b + h;
   const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
@@ -279,16 +283,15 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, const State<T>& s
   const T gb = T(sp.gamma * sp.beta);
   if (save) {
     g.s_prev[i] = si;
-    g.z_prev[i] = pad3(zi);
+    g.z_prev[i] = zi;
   }
-  st.s(i) = pad3(sn);
-  st.z(i) = pad3(V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y),
-                       zi.z - gb * (ti.z - sn.z)});
+  st.s(i) = sn;
+  st.z(i) = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
   if (p_out) {
     *p_out = pi;
     *q_out = qi;
     *t_out = ti;
-    *s_out = pad3(sn);
+    *s_out = sn;
   }
 }
 
@@ -300,7 +303,7 @@ template <typename T>
 __device__ __forceinline__ void vertex_SP(const DevGraph<T>& g, const State<T>& st, int i,
                                           const SweepParams& sp) {
   Q4<T> pi, qi;
-  P4<T> ti, si;
+  V3<T> ti, si;
   POut<T> po = p_out_zero<T>();
   vertex_S(g, st, i, sp, false, &po, &pi, &qi, &ti, &si);
   vertex_P_own(g, st, i, sp, qi, ti, si, pi, st.lam(i), &po);
@@ -375,7 +378,7 @@ hipError_t launch_phase_sweeps(const DevGraph<T>& g, int k, const SweepParams& s
 // sweep: p, q and t are read by their owner and gathered by neighbours in
 // two phases each, s in one, lambda and z only by their owner.  A graph of
 // n vertices keeps the first kSlots of p, q, t, s, lambda, z there, kSlots
-// the most whose n x kSlots slots fit the launch's LDS.
+// the most that fit the launch's LDS (state_lds_bytes).
 // ---------------------------------------------------------------------------
 template <int kSlots, typename T>
 __device__ __forceinline__ void graph_sweeps(const DevGraph<T>& g, int v0, int v1, int k,
@@ -409,8 +412,9 @@ __global__ void __launch_bounds__(1024) k_graph_sweeps(DevGraph<T> g,
   const int v0 = voff[gr], v1 = voff[gr + 1];
   if (sp.active && !sp.active[gr]) return;
   if (sp.beta_g) sp.beta = sp.beta_g[gr];
-  const size_t per = size_t(v1 - v0) * sizeof(Q4<T>);
-  const int slots = int(std::min<size_t>(6, size_t(lds_bytes) / per));
+  const size_t n = size_t(v1 - v0);
+  int slots = 0;
+  while (slots < 6 && state_lds_bytes<T>(slots + 1, n) <= size_t(lds_bytes)) ++slots;
   switch (slots) {
     case 6: graph_sweeps<6, T>(g, v0, v1, k, sp, lds_raw); break;
     case 5: graph_sweeps<5, T>(g, v0, v1, k, sp, lds_raw); break;
@@ -428,11 +432,10 @@ template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
                                int G, int k, const SweepParams& sp, int block, int max_n,
                                int lds, hipStream_t st) {
-  static_assert(sizeof(Q4<T>) == sizeof(P4<T>), "one slot size for every state array");
   if (G <= 0 || k <= 0) return hipSuccess;
   if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
   // enough for all six arrays of the largest graph, within the 160 KiB of a CU
-  size_t bytes = lds ? std::min(kLdsBytes, 6 * sizeof(Q4<T>) * size_t(max_n)) : 0;
+  size_t bytes = lds ? std::min(kLdsBytes, state_lds_bytes<T>(6, size_t(max_n))) : 0;
   if (bytes && hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps<T>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize,
                                    int(bytes)) != hipSuccess) {

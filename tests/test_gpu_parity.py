@@ -322,12 +322,13 @@ def test_graph_replays_equal_eager_launches(pgo, prec):
 
 def test_lds_residency_thresholds_bitwise(pgo):
     """Graphs on both sides of every LDS residency threshold of the per-graph
-    kernel (160 KiB of 16-byte FP32 slots: all six state arrays up to 1706
-    poses, five to 2048, four to 2560, three to 3413, two to 5120, one
-    above; FP64 slots are twice as wide; the chordal model's arrays have
-    their own widths) give the same bits as the per-phase schedule, whose
-    state stays in memory, for every model and both precisions."""
-    sizes = [1706, 1707, 2048, 2049, 2560, 2561, 3413, 3414, 5120, 5121]
+    kernel (160 KiB; FP32 quaternions take 16 bytes a pose, 3-vectors 12:
+    all six state arrays up to 1950 poses, five to 2275, four to 2925, three
+    to 3723, two to 5120, one above; FP64 arrays are twice as wide; the
+    chordal model's arrays have their own widths) give the same bits as the
+    per-phase schedule, whose state stays in memory, for every model and
+    both precisions."""
+    sizes = [1950, 1951, 2275, 2276, 2925, 2926, 3723, 3724, 5120, 5121]
     graphs = [S.circle(n, n_closures=n // 2, sigma_R=0.05, sigma_t=0.05, seed=k)
               for k, n in enumerate(sizes)]
     b = S.Batch(graphs)
