@@ -33,9 +33,10 @@ struct Sym3 {
   A xx, xy, xz, yy, yz, zz;
 };
 
+// from the two halves of the upper triangle, (xx, xy, xz) and (yy, yz, zz)
 template <typename A, typename T>
-__device__ __forceinline__ Sym3<A> sym3(const P4<T>& a, const P4<T>& b) {
-  return {A(a.x), A(a.y), A(a.z), A(a.u), A(b.x), A(b.y)};
+__device__ __forceinline__ Sym3<A> sym3(const V3<T>& a, const V3<T>& b) {
+  return {A(a.x), A(a.y), A(a.z), A(b.x), A(b.y), A(b.z)};
 }
 
 template <typename A>
@@ -383,7 +384,7 @@ __device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
   struct OutE {
     P4<T> tt;
     V3<T> tj;
-    P4<T> Sa, Sb;
+    V3<T> Sa, Sb;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1],
@@ -420,7 +421,9 @@ __device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
   const A pp[4] = {pi.w, pi.x, pi.y, pi.z};
   A x[4];
   trs4(M, bv, pp, x);
-  st.p(i) = Q4<T>{T(x[0]), T(x[1]), T(x[2]), T(x[3])};
+  // the solvers stop within ~1e-14 of the sphere; the update lies on it
+  const A nx = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2] + x[3] * x[3]);
+  st.p(i) = Q4<T>{T(x[0] / nx), T(x[1] / nx), T(x[2] / nx), T(x[3] / nx)};
 }
 
 template <typename T>
@@ -436,7 +439,7 @@ __device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, const State<T>& s
   struct OutE {
     P4<T> tt;
     V3<T> tj;
-    P4<T> Sa, Sb;
+    V3<T> Sa, Sb;
     Q4<T> pj, w;
   };
   edge_loop(
@@ -485,7 +488,7 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
   struct InE {
     P4<T> tt;
     V3<T> sl;
-    P4<T> Sa, Sb;
+    V3<T> Sa, Sb;
     Q4<T> ql, pl;
   };
   edge_loop(
@@ -520,7 +523,7 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& s
   struct OutE {
     P4<T> tt;
     V3<T> tj;
-    P4<T> Sa, Sb;
+    V3<T> Sa, Sb;
   };
   edge_loop(
       g.o_ptr[i], g.o_ptr[i + 1],
@@ -642,19 +645,19 @@ __global__ void __launch_bounds__(kMaxBlockGraphA) k_graph_sweeps_a(
   }
 }
 
-// edge records: tt = (t~, c_e), S_e as (xx, xy, xz, yy), (yz, zz, 0, 0)
+// edge records: tt = (t~, c_e), S_e as (xx, xy, xz), (yy, yz, zz)
 template <typename T>
 __global__ void k_fill_edges_a(const int32_t* __restrict__ perm, const double* __restrict__ tm,
                                const double* __restrict__ S9, int64_t m, P4<T>* __restrict__ tt,
-                               P4<T>* __restrict__ Sa, P4<T>* __restrict__ Sb) {
+                               V3<T>* __restrict__ Sa, V3<T>* __restrict__ Sb) {
   const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= m) return;
   const int64_t e = perm[k];
   const double* S = S9 + 9 * e;
   const double c = (S[0] + S[4] + S[8]) / 3.0;
   tt[k] = P4<T>{T(tm[3 * e]), T(tm[3 * e + 1]), T(tm[3 * e + 2]), T(c)};
-  Sa[k] = P4<T>{T(S[0]), T(S[1]), T(S[2]), T(S[4])};
-  Sb[k] = P4<T>{T(S[5]), T(S[8]), T(0), T(0)};
+  Sa[k] = V3<T>{T(S[0]), T(S[1]), T(S[2])};
+  Sb[k] = V3<T>{T(S[4]), T(S[5]), T(S[8])};
 }
 
 // 2 sum_in S_e and 2 sum_out S_e per vertex (FP64 sums)
@@ -663,9 +666,9 @@ __global__ void k_vertex_consts_a(int32_t n, const int32_t* __restrict__ o_ptr,
                                   const int32_t* __restrict__ o_perm,
                                   const int32_t* __restrict__ i_ptr,
                                   const int32_t* __restrict__ i_perm,
-                                  const double* __restrict__ S9, P4<T>* __restrict__ cTa,
-                                  P4<T>* __restrict__ cTb, P4<T>* __restrict__ cSa,
-                                  P4<T>* __restrict__ cSb) {
+                                  const double* __restrict__ S9, V3<T>* __restrict__ cTa,
+                                  V3<T>* __restrict__ cTb, V3<T>* __restrict__ cSa,
+                                  V3<T>* __restrict__ cSb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double so[6] = {0, 0, 0, 0, 0, 0}, si[6] = {0, 0, 0, 0, 0, 0};
@@ -674,10 +677,10 @@ __global__ void k_vertex_consts_a(int32_t n, const int32_t* __restrict__ o_ptr,
     for (int c = 0; c < 6; ++c) so[c] += S9[9 * int64_t(o_perm[k]) + pick[c]];
   for (int k = i_ptr[i]; k < i_ptr[i + 1]; ++k)
     for (int c = 0; c < 6; ++c) si[c] += S9[9 * int64_t(i_perm[k]) + pick[c]];
-  cTa[i] = P4<T>{T(2 * si[0]), T(2 * si[1]), T(2 * si[2]), T(2 * si[3])};
-  cTb[i] = P4<T>{T(2 * si[4]), T(2 * si[5]), T(0), T(0)};
-  cSa[i] = P4<T>{T(2 * so[0]), T(2 * so[1]), T(2 * so[2]), T(2 * so[3])};
-  cSb[i] = P4<T>{T(2 * so[4]), T(2 * so[5]), T(0), T(0)};
+  cTa[i] = V3<T>{T(2 * si[0]), T(2 * si[1]), T(2 * si[2])};
+  cTb[i] = V3<T>{T(2 * si[3]), T(2 * si[4]), T(2 * si[5])};
+  cSa[i] = V3<T>{T(2 * so[0]), T(2 * so[1]), T(2 * so[2])};
+  cSb[i] = V3<T>{T(2 * so[3]), T(2 * so[4]), T(2 * so[5])};
 }
 
 inline dim3 grid_of(int64_t count, int block) { return dim3(unsigned((count + block - 1) / block)); }
@@ -727,7 +730,7 @@ hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, cons
 
 template <typename T>
 hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const double* S9, int64_t m,
-                               P4<T>* tt, P4<T>* Sa, P4<T>* Sb, hipStream_t st) {
+                               P4<T>* tt, V3<T>* Sa, V3<T>* Sb, hipStream_t st) {
   if (m <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_fill_edges_a<T>), grid_of(m, 256), dim3(256), 0, st, perm, tm, S9, m, tt,
                      Sa, Sb);
@@ -737,7 +740,7 @@ hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const doub
 template <typename T>
 hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
                                   const int32_t* i_ptr, const int32_t* i_perm, const double* S9,
-                                  P4<T>* cTa, P4<T>* cTb, P4<T>* cSa, P4<T>* cSb, hipStream_t st) {
+                                  V3<T>* cTa, V3<T>* cTb, V3<T>* cSa, V3<T>* cSb, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_vertex_consts_a<T>), grid_of(n, 256), dim3(256), 0, st, n, o_ptr, o_perm,
                      i_ptr, i_perm, S9, cTa, cTb, cSa, cSb);
@@ -751,10 +754,10 @@ hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t
                                                const int32_t*, int, int, const SweepParams&,      \
                                                int, int, int, hipStream_t);                       \
   template hipError_t launch_fill_edges_a<T>(const int32_t*, const double*, const double*,       \
-                                             int64_t, P4<T>*, P4<T>*, P4<T>*, hipStream_t);       \
+                                             int64_t, P4<T>*, V3<T>*, V3<T>*, hipStream_t);       \
   template hipError_t launch_vertex_consts_a<T>(int32_t, const int32_t*, const int32_t*,         \
                                                 const int32_t*, const int32_t*, const double*,   \
-                                                P4<T>*, P4<T>*, P4<T>*, P4<T>*, hipStream_t);
+                                                V3<T>*, V3<T>*, V3<T>*, V3<T>*, hipStream_t);
 
 PGO_ANISO_INST(float)
 PGO_ANISO_INST(double)

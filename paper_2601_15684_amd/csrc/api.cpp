@@ -211,10 +211,10 @@ bool lds_fits(const pgo_graph*) { return true; }
 template <typename T>
 DevAniso<T> viewa(const pgo_graph* g) {
   return DevAniso<T>{view<T>(g),
-                     static_cast<const P4<T>*>(g->o_Sa), static_cast<const P4<T>*>(g->o_Sb),
-                     static_cast<const P4<T>*>(g->i_Sa), static_cast<const P4<T>*>(g->i_Sb),
-                     static_cast<const P4<T>*>(g->cTa), static_cast<const P4<T>*>(g->cTb),
-                     static_cast<const P4<T>*>(g->cSa), static_cast<const P4<T>*>(g->cSb)};
+                     static_cast<const V3<T>*>(g->o_Sa), static_cast<const V3<T>*>(g->o_Sb),
+                     static_cast<const V3<T>*>(g->i_Sa), static_cast<const V3<T>*>(g->i_Sb),
+                     static_cast<const V3<T>*>(g->cTa), static_cast<const V3<T>*>(g->cTb),
+                     static_cast<const V3<T>*>(g->cSa), static_cast<const V3<T>*>(g->cSb)};
 }
 
 // words of T per vertex of a rotation-like block (p, q, lambda and edge w)
@@ -335,10 +335,10 @@ pgo_status alloc_precision(pgo_graph* g) {
   if (g->aniso) {
     void** es[] = {&g->o_Sa, &g->o_Sb, &g->i_Sa, &g->i_Sb};
     for (void** v : es)
-      if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * m)) != PGO_OK) return s;
+      if ((s = dalloc_bytes(g, v, 3 * sizeof(T) * m)) != PGO_OK) return s;
     void** vs[] = {&g->cTa, &g->cTb, &g->cSa, &g->cSb};
     for (void** v : vs)
-      if ((s = dalloc_bytes(g, v, 4 * sizeof(T) * n)) != PGO_OK) return s;
+      if ((s = dalloc_bytes(g, v, 3 * sizeof(T) * n)) != PGO_OK) return s;
   }
   return PGO_OK;
 }
@@ -366,12 +366,12 @@ pgo_status prepare_precision(pgo_graph* g, const double* t0_dev) {
                                  static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
   if (g->aniso) {
     HIPCHK(launch_fill_edges_a<T>(g->o_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->o_tt),
-                                  static_cast<P4<T>*>(g->o_Sa), static_cast<P4<T>*>(g->o_Sb), st));
+                                  static_cast<V3<T>*>(g->o_Sa), static_cast<V3<T>*>(g->o_Sb), st));
     HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
-                                  static_cast<P4<T>*>(g->i_Sa), static_cast<P4<T>*>(g->i_Sb), st));
+                                  static_cast<V3<T>*>(g->i_Sa), static_cast<V3<T>*>(g->i_Sb), st));
     HIPCHK(launch_vertex_consts_a<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->S9,
-                                     static_cast<P4<T>*>(g->cTa), static_cast<P4<T>*>(g->cTb),
-                                     static_cast<P4<T>*>(g->cSa), static_cast<P4<T>*>(g->cSb), st));
+                                     static_cast<V3<T>*>(g->cTa), static_cast<V3<T>*>(g->cTb),
+                                     static_cast<V3<T>*>(g->cSa), static_cast<V3<T>*>(g->cSb), st));
   }
   HIPCHK(launch_init_state<T>(view<T>(g), g->p0, t0_dev, st));
   return PGO_OK;
@@ -893,12 +893,12 @@ pgo_status refill_edges(pgo_graph* g) {
                                  static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
   if (g->aniso) {  // edge records (t~, c) and the information sums
     HIPCHK(launch_fill_edges_a<T>(g->o_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->o_tt),
-                                  static_cast<P4<T>*>(g->o_Sa), static_cast<P4<T>*>(g->o_Sb), st));
+                                  static_cast<V3<T>*>(g->o_Sa), static_cast<V3<T>*>(g->o_Sb), st));
     HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
-                                  static_cast<P4<T>*>(g->i_Sa), static_cast<P4<T>*>(g->i_Sb), st));
+                                  static_cast<V3<T>*>(g->i_Sa), static_cast<V3<T>*>(g->i_Sb), st));
     HIPCHK(launch_vertex_consts_a<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->S9,
-                                     static_cast<P4<T>*>(g->cTa), static_cast<P4<T>*>(g->cTb),
-                                     static_cast<P4<T>*>(g->cSa), static_cast<P4<T>*>(g->cSb), st));
+                                     static_cast<V3<T>*>(g->cTa), static_cast<V3<T>*>(g->cTb),
+                                     static_cast<V3<T>*>(g->cSa), static_cast<V3<T>*>(g->cSb), st));
   }
   return PGO_OK;
 }

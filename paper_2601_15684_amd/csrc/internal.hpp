@@ -224,14 +224,14 @@ hipError_t launch_poses(const DevGraph<T>& g, double* R, double* t, hipStream_t 
 template <typename T>
 struct DevAniso {
   DevGraph<T> g;
-  const P4<T>* o_Sa;
-  const P4<T>* o_Sb;
-  const P4<T>* i_Sa;
-  const P4<T>* i_Sb;
-  const P4<T>* cTa;
-  const P4<T>* cTb;
-  const P4<T>* cSa;
-  const P4<T>* cSb;
+  const V3<T>* o_Sa;
+  const V3<T>* o_Sb;
+  const V3<T>* i_Sa;
+  const V3<T>* i_Sb;
+  const V3<T>* cTa;
+  const V3<T>* cTb;
+  const V3<T>* cSa;
+  const V3<T>* cSb;
 };
 template <typename T>
 hipError_t launch_phase_sweeps_a(const DevAniso<T>& a, int k, const SweepParams& sp, int block,
@@ -244,11 +244,11 @@ hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, cons
                                  hipStream_t st);
 template <typename T>
 hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const double* S9, int64_t m,
-                               P4<T>* tt, P4<T>* Sa, P4<T>* Sb, hipStream_t st);
+                               P4<T>* tt, V3<T>* Sa, V3<T>* Sb, hipStream_t st);
 template <typename T>
 hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
                                   const int32_t* i_ptr, const int32_t* i_perm, const double* S9,
-                                  P4<T>* cTa, P4<T>* cTb, P4<T>* cSa, P4<T>* cSb, hipStream_t st);
+                                  V3<T>* cTa, V3<T>* cTb, V3<T>* cSa, V3<T>* cSb, hipStream_t st);
 
 // Chordal model (chordal.hip): sweeps, preparation and state transfer.
 template <typename T>
