@@ -418,8 +418,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: the batched sweep shards by whole graphs with no "
-              "exchange, so this build has no multi-GPU leg (run with --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: the batched sweep would shard by whole graphs with "
+              "no exchange between GPUs, and no multi-GPU leg is measured here (run with --gpus 1).",
+              file=sys.stderr)
         sys.exit(2)
 
     # inputs first: the generator forks worker processes, which must happen
