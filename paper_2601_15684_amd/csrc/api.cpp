@@ -98,7 +98,7 @@ struct pgo_graph {
   int sched = PGO_SCHED_PHASE;
   int block_phase = 256;
   int block_graph = 256;
-  int graph_lds = 1;  // per-graph kernel keeps graphs' state in LDS (quaternion model)
+  int graph_lds = 1;  // per-graph kernels keep each graph's state in LDS as far as it fits
   bool have_prev = false;
   // captured launch sequence of the per-phase schedule
   hipGraphExec_t gexec = nullptr;
@@ -202,11 +202,6 @@ DevChordal<T> viewc(const pgo_graph* g) {
   d.z_prev = static_cast<V3<T>*>(g->z_prev);
   return d;
 }
-
-// Whether the per-graph kernel can keep graphs' state in LDS for a launch
-// (every model; each graph keeps what fits, see launch_graph_sweeps,
-// launch_graph_sweeps_c and launch_graph_sweeps_a).
-bool lds_fits(const pgo_graph*) { return true; }
 
 template <typename T>
 DevAniso<T> viewa(const pgo_graph* g) {
@@ -1279,7 +1274,7 @@ pgo_status pgo_info(pgo_graph* g, int64_t* n, int64_t* m, int32_t* G, int32_t* p
   if (schedule) *schedule = g->sched;
   if (block) *block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
   if (model) *model = g->opt.model;
-  if (lds) *lds = (g->sched == PGO_SCHED_GRAPH && g->graph_lds && lds_fits(g)) ? 1 : 0;
+  if (lds) *lds = (g->sched == PGO_SCHED_GRAPH && g->graph_lds) ? 1 : 0;
   return PGO_OK;
 }
 
@@ -1303,7 +1298,7 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
     for (int b : {128, 256, 512, 1024}) {
       if (b > bmax_graph) continue;
       cands.push_back({PGO_SCHED_GRAPH, b, 0});
-      if (lds_fits(g)) cands.push_back({PGO_SCHED_GRAPH, b, 1});
+      cands.push_back({PGO_SCHED_GRAPH, b, 1});
     }
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
