@@ -92,9 +92,17 @@ def test_batched_offsets_validated(pgo):
 
 
 def test_null_handle_calls(pgo):
+    import ctypes as C
+    lib = pgo.lib()
+    buf = (C.c_double * 8)()
     for fn in (lambda: pgo.pgo_iterate(None, 1, 1.0, 1.0), lambda: pgo.pgo_set_stream(None, 0)):
         with pytest.raises(pgo.PgoError):
             fn()
+    # every reduction entry point refuses a null handle before touching a device
+    for call in (lambda: lib.pgo_cost(None, buf), lambda: lib.pgo_residuals(None, buf),
+                 lambda: lib.pgo_merit(None, buf), lambda: lib.pgo_evaluate(None, buf, buf, buf),
+                 lambda: lib.pgo_evaluate(None, None, None, None)):
+        assert call() == 1  # PGO_EINVAL
     pgo.pgo_destroy(None)
 
 

@@ -76,3 +76,18 @@ def test_batched_subset_reproducible():
     for gr in a.graphs:
         assert 50 <= gr.n <= 5000
         assert gr.ei.max() < gr.n and gr.ej.max() < gr.n and np.all(gr.ei != gr.ej)
+
+
+def test_random_information_matrices():
+    """random_info: symmetric positive definite, eigenvalues tau_e x [aniso^-1/2,
+    aniso^1/2], seeded."""
+    import pgo_synth as S
+    tau = np.linspace(1.0, 100.0, 500)
+    A = S.random_info(500, tau, 10.0, seed=3)
+    assert A.shape == (500, 3, 3)
+    assert np.abs(A - np.transpose(A, (0, 2, 1))).max() <= 1e-12 * np.abs(A).max()
+    w = np.linalg.eigvalsh(A) / tau[:, None]
+    assert w.min() >= 10.0 ** -0.5 * (1 - 1e-12) and w.max() <= 10.0 ** 0.5 * (1 + 1e-12)
+    assert np.array_equal(A, S.random_info(500, tau, 10.0, seed=3))
+    iso = S.random_info(20, np.full(20, 7.0), 1.0, seed=1)
+    assert np.allclose(iso, 7.0 * np.eye(3), atol=1e-12)
