@@ -94,7 +94,8 @@ def step_q(P, st, p_new, beta, h=DEFAULT_H):
 
 
 def _c(p, q, tm, tail):
-    """c_e = Im(q_l t~_e p_l^*) with l the tail of edge e (G2 reading of App. B.3)."""
+    """c_e = Im(q_l t~_e p_l^*) with l the tail of edge e (App. B.3 prints the
+    indices of an out-edge; the t-subproblem sums over in-edges)."""
     return qmul(qmul(q[tail], hat(tm)), qconj(p[tail]))[:, 1:]
 
 
