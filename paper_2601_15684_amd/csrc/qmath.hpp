@@ -13,8 +13,9 @@ struct alignas(4 * sizeof(T)) Q4 {
   T w, x, y, z;
 };
 
-// 3-vector stored in a 16/32-byte slot; u is a spare component (0 for the
-// state vectors t, s, z; tau for an edge's (tau t~, tau) record).
+// A 3-vector and a fourth word in one aligned 16/32-byte record: an edge's
+// (tau t~, tau), or the information model's (t~, c_e).  State 3-vectors
+// (t, s, z) are stored packed as V3.
 template <typename T>
 struct alignas(4 * sizeof(T)) P4 {
   T x, y, z, u;
