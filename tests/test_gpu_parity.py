@@ -365,3 +365,32 @@ def test_relaxation_steps_of_the_sphere_workload(pgo, gamma):
     for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
         got, _, _ = gpu_run(pgo, g, 10, beta, gamma, precision=prec)
         assert_parity(scaled_err(got, ref, beta), tol, f"sphere/{prec}/gamma={gamma}")
+
+
+def test_degenerate_graphs_in_a_batch(pgo):
+    """A batch holding a single pose without edges, a two-pose graph with one
+    edge and an ordinary graph: the per-graph kernel (state in LDS) and the
+    per-phase schedule agree bit for bit, and each graph matches the oracle
+    run alone."""
+    single = S.tree(3, seed=4)
+    single.n = 1
+    single.R0, single.t0 = single.R0[:1], single.t0[:1]
+    single.R_gt, single.t_gt = single.R_gt[:1], single.t_gt[:1]
+    single.ei, single.ej = single.ei[:0], single.ej[:0]
+    single.Rm, single.tm, single.kappa, single.tau = (single.Rm[:0], single.tm[:0],
+                                                      single.kappa[:0], single.tau[:0])
+    graphs = [single, S.tree(2, seed=5), S.make_config("circle-100")]
+    b = S.Batch(graphs)
+    betas = np.array([1.0, 0.05 * abar(graphs[1]), 0.01 * abar(graphs[2])])
+    voff, _ = b.offsets()
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-4)):
+        got = {}
+        for sched, block in (("phase", 64), ("graph", 128)):
+            with pgo.PoseGraph.from_batch(b, precision=prec, schedule=sched, block=block) as h:
+                h.iterate(10, betas, GAMMA)
+                got[sched] = h.state()
+        assert np.array_equal(got["phase"], got["graph"]), prec
+        for k, gr in enumerate(graphs):
+            _, st, _ = oracle_run(gr, 10, betas[k])
+            assert_parity(scaled_err(got["graph"][voff[k]:voff[k + 1]], pack(st), betas[k]), tol,
+                          f"{prec}/graph {k}")
