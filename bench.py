@@ -398,8 +398,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10,
                     help="timed solve chunks (0: only the hipEvent-timed plain launches)")
-    ap.add_argument("--warmup", type=int, default=4,
-                    help="untimed steps of the merit-checked solve that settle each graph's beta")
+    ap.add_argument("--warmup", type=int, default=16,
+                    help="untimed chunks of the merit-checked solve that settle each graph's beta "
+                         "(with 4, a few graphs of the batch still rise at the settled penalty)")
     ap.add_argument("--sweeps", type=int, default=50, help="sweeps per persistent launch (one step)")
     ap.add_argument("--graphs", type=int, default=4096)
     ap.add_argument("--workers", type=int, default=16)
