@@ -93,6 +93,7 @@ struct pgo_graph {
   int n_ech = 0, n_vch = 0;
   int64_t *ec_beg = nullptr, *ec_end = nullptr, *vc_beg = nullptr, *vc_end = nullptr;
   int32_t *g_ec_off = nullptr, *g_vc_off = nullptr;
+  int32_t *ec_gid = nullptr, *vc_gid = nullptr;  // graph of each reduction chunk
   double *part_e = nullptr, *part_v = nullptr, *red_out = nullptr;
   double* iobuf = nullptr;  // n x state width doubles, allocated on first use
   int sched = PGO_SCHED_PHASE;
@@ -280,16 +281,18 @@ pgo_status check_inputs(int32_t G, const int64_t* voff, const int64_t* eoff, con
 
 pgo_status build_chunks(pgo_graph* g) {
   std::vector<int64_t> eb, ee, vb, ve;
-  std::vector<int32_t> goe(g->G + 1, 0), gov(g->G + 1, 0);
+  std::vector<int32_t> goe(g->G + 1, 0), gov(g->G + 1, 0), egid, vgid;
   for (int32_t k = 0; k < g->G; ++k) {
     for (int64_t a = g->eoff_h[k]; a < g->eoff_h[k + 1]; a += kChunk) {
       eb.push_back(a);
       ee.push_back(std::min(a + kChunk, g->eoff_h[k + 1]));
+      egid.push_back(k);
     }
     goe[k + 1] = int32_t(eb.size());
     for (int64_t a = g->voff_h[k]; a < g->voff_h[k + 1]; a += kChunk) {
       vb.push_back(a);
       ve.push_back(std::min(a + kChunk, g->voff_h[k + 1]));
+      vgid.push_back(k);
     }
     gov[k + 1] = int32_t(vb.size());
   }
@@ -302,6 +305,8 @@ pgo_status build_chunks(pgo_graph* g) {
   if ((s = upload(g, &g->vc_end, ve.data(), ve.size())) != PGO_OK) return s;
   if ((s = upload(g, &g->g_ec_off, goe.data(), goe.size())) != PGO_OK) return s;
   if ((s = upload(g, &g->g_vc_off, gov.data(), gov.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->ec_gid, egid.data(), egid.size())) != PGO_OK) return s;
+  if ((s = upload(g, &g->vc_gid, vgid.data(), vgid.size())) != PGO_OK) return s;
   if ((s = dalloc(g, &g->part_e, size_t(kEdgeVals) * std::max(1, g->n_ech))) != PGO_OK) return s;
   if ((s = dalloc(g, &g->part_v, size_t(kVertVals) * std::max(1, g->n_vch))) != PGO_OK) return s;
   if ((s = dalloc(g, &g->red_out, size_t(kRedVals) * g->G)) != PGO_OK) return s;
@@ -696,26 +701,33 @@ pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int 
 
 // Per-graph reduction values (RedIdx order).  Unless allow_nonfinite, a
 // non-finite value anywhere is reported as PGO_ENUMERIC.
-pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite = false) {
+// active (device, G flags) restricts the work to the graphs flagged 1; the
+// others report zeros.
+pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite = false,
+                  const int32_t* active = nullptr) {
   HIPCHK(hipSetDevice(g->device));
   EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9, g->S9};
   hipError_t he;
   if (g->chordal && g->opt.precision == PGO_FP64)
-    he = launch_reduce_c<double>(viewc<double>(g), e, g->have_prev, g->ec_beg, g->ec_end, g->n_ech,
-                                 g->vc_beg, g->vc_end, g->n_vch, g->part_e, g->part_v,
-                                 g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
+    he = launch_reduce_c<double>(viewc<double>(g), e, g->have_prev, g->ec_gid, g->ec_beg,
+                                 g->ec_end, g->n_ech, g->vc_gid, g->vc_beg, g->vc_end, g->n_vch,
+                                 g->part_e, g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out,
+                                 active, g->stream);
   else if (g->chordal)
-    he = launch_reduce_c<float>(viewc<float>(g), e, g->have_prev, g->ec_beg, g->ec_end, g->n_ech,
-                                g->vc_beg, g->vc_end, g->n_vch, g->part_e, g->part_v, g->g_ec_off,
-                                g->g_vc_off, g->G, g->red_out, g->stream);
+    he = launch_reduce_c<float>(viewc<float>(g), e, g->have_prev, g->ec_gid, g->ec_beg, g->ec_end,
+                                g->n_ech, g->vc_gid, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
+                                g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, active,
+                                g->stream);
   else if (g->opt.precision == PGO_FP64)
-    he = launch_reduce<double>(view<double>(g), e, g->have_prev, nullptr, g->ec_beg, g->ec_end,
-                               g->n_ech, nullptr, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
-                               g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
+    he = launch_reduce<double>(view<double>(g), e, g->have_prev, g->ec_gid, g->ec_beg, g->ec_end,
+                               g->n_ech, g->vc_gid, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
+                               g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, active,
+                               g->stream);
   else
-    he = launch_reduce<float>(view<float>(g), e, g->have_prev, nullptr, g->ec_beg, g->ec_end,
-                              g->n_ech, nullptr, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
-                              g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, g->stream);
+    he = launch_reduce<float>(view<float>(g), e, g->have_prev, g->ec_gid, g->ec_beg, g->ec_end,
+                              g->n_ech, g->vc_gid, g->vc_beg, g->vc_end, g->n_vch, g->part_e,
+                              g->part_v, g->g_ec_off, g->g_vc_off, g->G, g->red_out, active,
+                              g->stream);
   if (he != hipSuccess) return hip_fail(he, "reduce");
   out.resize(size_t(kRedVals) * g->G);
   HIPCHK(hipMemcpyAsync(out.data(), g->red_out, out.size() * sizeof(double),
@@ -757,18 +769,25 @@ void state_array_bytes(const pgo_graph* g, size_t out[6]) {
   for (int k = 3; k < 6; ++k) out[k] = 3 * w;
 }
 
-pgo_status snapshot(pgo_graph* g) {
+// Copies the state into the snapshot arrays: every vertex, or (active, G
+// device flags) the vertices of the flagged graphs only.
+pgo_status snapshot(pgo_graph* g, const int32_t* active = nullptr) {
   size_t vb[6];
   state_array_bytes(g, vb);
   void* cur[6] = {g->p, g->q, g->lam, g->t, g->s, g->z};
-  for (int k = 0; k < 6; ++k) {
-    const size_t bytes = vb[k] * size_t(g->n);
+  for (int k = 0; k < 6; ++k)
     if (!g->snap[k]) {
-      pgo_status s = dalloc_bytes(g, &g->snap[k], bytes);
+      pgo_status s = dalloc_bytes(g, &g->snap[k], vb[k] * size_t(g->n));
       if (s != PGO_OK) return s;
     }
-    HIPCHK(launch_copy(g->snap[k], cur[k], bytes, g->stream));
+  if (active) {
+    int words[6];
+    for (int k = 0; k < 6; ++k) words[k] = int(vb[k] / 4);
+    HIPCHK(launch_restore_words(int32_t(g->n), g->gid, active, g->snap, cur, words, g->stream));
+    return PGO_OK;
   }
+  for (int k = 0; k < 6; ++k)
+    HIPCHK(launch_copy(g->snap[k], cur[k], vb[k] * size_t(g->n), g->stream));
   return PGO_OK;
 }
 
@@ -1117,11 +1136,14 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
       any = any || active[size_t(j)];
     }
     if (!any) break;
-    if (adapt && (s = snapshot(g)) != PGO_OK) return s;
+    // snapshots and reductions cover the running graphs only
+    HIPCHK(hipMemcpyAsync(g->active_dev, active.data(), sizeof(int32_t) * G,
+                          hipMemcpyHostToDevice, g->stream));
+    if (adapt && (s = snapshot(g, g->active_dev)) != PGO_OK) return s;
     if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta, active.data())) !=
         PGO_OK)
       return s;
-    if ((s = reduce(g, r, true)) != PGO_OK) return s;
+    if ((s = reduce(g, r, true, g->active_dev)) != PGO_OK) return s;
     bool any_restore = false;
     for (int32_t j = 0; j < G; ++j) {
       flags[size_t(j)] = 0;

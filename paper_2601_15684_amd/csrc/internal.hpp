@@ -380,20 +380,23 @@ enum RedIdx {
 };
 constexpr int kEdgeVals = 2;  // kCost, kSplit
 constexpr int kVertVals = 9;  // kPQ2 .. kZTS
+// ec_graph / vc_graph: graph of each edge / vertex chunk; with active given,
+// chunks of graphs whose flag is 0 skip their work and report zeros.
 template <typename T>
 hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
                          const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,
                          int n_echunks, const int32_t* vc_graph, const int64_t* vc_beg,
                          const int64_t* vc_end, int n_vchunks, double* partial_e,
                          double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
-                         int G, double* out, hipStream_t st);
+                         int G, double* out, const int32_t* active, hipStream_t st);
 
 template <typename T>
 hipError_t launch_reduce_c(const DevChordal<T>& g, const EdgeF64& e, int have_prev,
-                           const int64_t* ec_beg, const int64_t* ec_end, int n_echunks,
-                           const int64_t* vc_beg, const int64_t* vc_end, int n_vchunks,
-                           double* partial_e, double* partial_v, const int32_t* g_ec_off,
-                           const int32_t* g_vc_off, int G, double* out, hipStream_t st);
+                           const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,
+                           int n_echunks, const int32_t* vc_graph, const int64_t* vc_beg,
+                           const int64_t* vc_end, int n_vchunks, double* partial_e,
+                           double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
+                           int G, double* out, const int32_t* active, hipStream_t st);
 
 // ---------------------------------------------------------------------------
 // Reverse mode (adjoint.hip)

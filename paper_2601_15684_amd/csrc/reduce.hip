@@ -72,15 +72,24 @@ __device__ double edge_split(const DevGraph<T>& g, const EdgeF64& E, int64_t e) 
          E.kappa[e] * (a0 * a0 + a.x * a.x + a.y * a.y + a.z * a.z);
 }
 
+// Chunks of graphs whose flag is 0 skip their work (partials 0), when
+// active is given; chunk c belongs to graph gid[c].
+struct ChunkMask {
+  const int32_t* gid;
+  const int32_t* active;
+  __device__ __forceinline__ bool skip(int c) const { return active && !active[gid[c]]; }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(kRB) k_red_edges(DevGraph<T> g, EdgeF64 E,
                                                     const int64_t* __restrict__ beg,
                                                     const int64_t* __restrict__ end,
-                                                    double* __restrict__ partial) {
+                                                    ChunkMask mask, double* __restrict__ partial) {
   __shared__ double sh[kEdgeVals][kRB];
   double v[kEdgeVals] = {0.0, 0.0};
   const int c = blockIdx.x;
-  for (int64_t e = beg[c] + threadIdx.x; e < end[c]; e += kRB) {
+  const int64_t stop = mask.skip(c) ? beg[c] : end[c];
+  for (int64_t e = beg[c] + threadIdx.x; e < stop; e += kRB) {
     v[0] += edge_cost(g, E, e);
     v[1] += edge_split(g, E, e);
   }
@@ -119,11 +128,13 @@ template <typename T>
 __global__ void __launch_bounds__(kRB) k_red_vertices(DevGraph<T> g, int have_prev,
                                                        const int64_t* __restrict__ beg,
                                                        const int64_t* __restrict__ end,
+                                                       ChunkMask mask,
                                                        double* __restrict__ partial) {
   __shared__ double sh[kVertVals][kRB];
   double v[kVertVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int c = blockIdx.x;
-  for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
+  const int64_t stop = mask.skip(c) ? beg[c] : end[c];
+  for (int64_t i = beg[c] + threadIdx.x; i < stop; i += kRB) {
     v[0] += d2q(g.p[i], g.q[i]);
     v[1] += d2<T, V3<T>>(g.t[i], g.s[i]);
     v[7] += dotq(g.lam[i], g.p[i], g.q[i]);
@@ -196,11 +207,13 @@ template <typename T>
 __global__ void __launch_bounds__(kRB) k_red_edges_c(DevChordal<T> g, EdgeF64 E,
                                                       const int64_t* __restrict__ beg,
                                                       const int64_t* __restrict__ end,
+                                                      ChunkMask mask,
                                                       double* __restrict__ partial) {
   __shared__ double sh[kEdgeVals][kRB];
   double v[kEdgeVals] = {0.0, 0.0};
   const int c = blockIdx.x;
-  for (int64_t e = beg[c] + threadIdx.x; e < end[c]; e += kRB) {
+  const int64_t stop = mask.skip(c) ? beg[c] : end[c];
+  for (int64_t e = beg[c] + threadIdx.x; e < stop; e += kRB) {
     const int i = E.ei[e], j = E.ej[e];
     const R3<T> Pi = g.P[i], Pj = g.P[j];
     v[0] += edge_chordal(E, e, Pi, Pi, Pj, g.t[i], g.t[j]);
@@ -229,11 +242,13 @@ template <typename T>
 __global__ void __launch_bounds__(kRB) k_red_vertices_c(DevChordal<T> g, int have_prev,
                                                          const int64_t* __restrict__ beg,
                                                          const int64_t* __restrict__ end,
+                                                         ChunkMask mask,
                                                          double* __restrict__ partial) {
   __shared__ double sh[kVertVals][kRB];
   double v[kVertVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const int c = blockIdx.x;
-  for (int64_t i = beg[c] + threadIdx.x; i < end[c]; i += kRB) {
+  const int64_t stop = mask.skip(c) ? beg[c] : end[c];
+  for (int64_t i = beg[c] + threadIdx.x; i < stop; i += kRB) {
     v[0] += d2m(g.P[i], g.Q[i]);
     v[1] += d2<T, V3<T>>(g.t[i], g.s[i]);
     v[7] += dotm(g.L[i], g.P[i], g.Q[i]);
@@ -255,43 +270,46 @@ __global__ void __launch_bounds__(kRB) k_red_vertices_c(DevChordal<T> g, int hav
 
 template <typename T>
 hipError_t launch_reduce_c(const DevChordal<T>& g, const EdgeF64& e, int have_prev,
-                           const int64_t* ec_beg, const int64_t* ec_end, int n_echunks,
-                           const int64_t* vc_beg, const int64_t* vc_end, int n_vchunks,
-                           double* partial_e, double* partial_v, const int32_t* g_ec_off,
-                           const int32_t* g_vc_off, int G, double* out, hipStream_t st) {
+                           const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,
+                           int n_echunks, const int32_t* vc_graph, const int64_t* vc_beg,
+                           const int64_t* vc_end, int n_vchunks, double* partial_e,
+                           double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
+                           int G, double* out, const int32_t* active, hipStream_t st) {
   if (n_echunks > 0)
     hipLaunchKernelGGL((k_red_edges_c<T>), dim3(n_echunks), dim3(kRB), 0, st, g, e, ec_beg, ec_end,
-                       partial_e);
+                       ChunkMask{ec_graph, active}, partial_e);
   if (n_vchunks > 0)
     hipLaunchKernelGGL((k_red_vertices_c<T>), dim3(n_vchunks), dim3(kRB), 0, st, g, have_prev,
-                       vc_beg, vc_end, partial_v);
+                       vc_beg, vc_end, ChunkMask{vc_graph, active}, partial_v);
   hipLaunchKernelGGL(k_red_finish, dim3((G + 255) / 256), dim3(256), 0, st, partial_e, partial_v,
                      g_ec_off, g_vc_off, G, out);
   return hipGetLastError();
 }
 
 template hipError_t launch_reduce_c<float>(const DevChordal<float>&, const EdgeF64&, int,
-                                           const int64_t*, const int64_t*, int, const int64_t*,
-                                           const int64_t*, int, double*, double*, const int32_t*,
-                                           const int32_t*, int, double*, hipStream_t);
+                                           const int32_t*, const int64_t*, const int64_t*, int,
+                                           const int32_t*, const int64_t*, const int64_t*, int,
+                                           double*, double*, const int32_t*, const int32_t*, int,
+                                           double*, const int32_t*, hipStream_t);
 template hipError_t launch_reduce_c<double>(const DevChordal<double>&, const EdgeF64&, int,
-                                            const int64_t*, const int64_t*, int, const int64_t*,
-                                            const int64_t*, int, double*, double*, const int32_t*,
-                                            const int32_t*, int, double*, hipStream_t);
+                                            const int32_t*, const int64_t*, const int64_t*, int,
+                                            const int32_t*, const int64_t*, const int64_t*, int,
+                                            double*, double*, const int32_t*, const int32_t*, int,
+                                            double*, const int32_t*, hipStream_t);
 
 template <typename T>
 hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
-                         const int32_t* /*ec_graph*/, const int64_t* ec_beg, const int64_t* ec_end,
-                         int n_echunks, const int32_t* /*vc_graph*/, const int64_t* vc_beg,
+                         const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,
+                         int n_echunks, const int32_t* vc_graph, const int64_t* vc_beg,
                          const int64_t* vc_end, int n_vchunks, double* partial_e,
                          double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
-                         int G, double* out, hipStream_t st) {
+                         int G, double* out, const int32_t* active, hipStream_t st) {
   if (n_echunks > 0)
     hipLaunchKernelGGL((k_red_edges<T>), dim3(n_echunks), dim3(kRB), 0, st, g, e, ec_beg, ec_end,
-                       partial_e);
+                       ChunkMask{ec_graph, active}, partial_e);
   if (n_vchunks > 0)
     hipLaunchKernelGGL((k_red_vertices<T>), dim3(n_vchunks), dim3(kRB), 0, st, g, have_prev,
-                       vc_beg, vc_end, partial_v);
+                       vc_beg, vc_end, ChunkMask{vc_graph, active}, partial_v);
   hipLaunchKernelGGL(k_red_finish, dim3((G + 255) / 256), dim3(256), 0, st, partial_e, partial_v,
                      g_ec_off, g_vc_off, G, out);
   return hipGetLastError();
@@ -301,11 +319,11 @@ template hipError_t launch_reduce<float>(const DevGraph<float>&, const EdgeF64&,
                                          const int32_t*, const int64_t*, const int64_t*, int,
                                          const int32_t*, const int64_t*, const int64_t*, int,
                                          double*, double*, const int32_t*, const int32_t*, int,
-                                         double*, hipStream_t);
+                                         double*, const int32_t*, hipStream_t);
 template hipError_t launch_reduce<double>(const DevGraph<double>&, const EdgeF64&, int,
                                           const int32_t*, const int64_t*, const int64_t*, int,
                                           const int32_t*, const int64_t*, const int64_t*, int,
                                           double*, double*, const int32_t*, const int32_t*, int,
-                                          double*, hipStream_t);
+                                          double*, const int32_t*, hipStream_t);
 
 }  // namespace pgo
