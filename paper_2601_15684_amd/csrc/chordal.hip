@@ -390,8 +390,8 @@ __global__ void k_phase_c(DevChordal<T> g, SweepParams sp, int save) {
 // neighbours (s in T; P in Q and T), t and Q likewise with fewer reads, z and
 // Lambda only by their owner.  A graph keeps the first kArrays of
 // s, P, t, Q, z, Lambda whose slots fit.
-// Each array starts on a 16-byte boundary (the padded 3-vectors are read as
-// aligned 16/32-byte words).
+// Each array starts on a 16-byte boundary, which keeps the wide loads of
+// its records aligned.
 __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~size_t(15); }
 
 template <typename T>
