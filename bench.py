@@ -213,6 +213,39 @@ def solve_figure(r, steps):
                     "edge-iterations over wall time"}
 
 
+def stopping_leg(P, torch, cat, voff, eoff, betas, edges_per_graph, max_sweeps=1000, check=10,
+                 tol=1e-4):
+    """The experiments' stopping rule e < tol (App. E.1, tol 1e-4 as in the
+    experiments section) on the batch from its odometry start, chunks of
+    `check` sweeps, at most `max_sweeps`: evaluated inside the persistent
+    kernel (pgo_iterate_until, one launch) against the host loop of
+    pgo_solve without penalty control (one launch, reduction and host check
+    per chunk).  Both stop every graph after the same sweeps."""
+    opt = P.pgo_default_options(precision="fp32", schedule="graph", block=1024)
+    h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"], cat["ej"],
+                             cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"], cat["tau"], opt)
+    s0 = P.pgo_get_state(h)
+    P.pgo_iterate_until(h, check, check, betas, GAMMA, tol)  # warm-up of the launch path
+    out = {"workload": "batched-4096", "tol": tol, "check_every": check, "max_sweeps": max_sweeps}
+    for label in ("in_kernel", "host_loop"):
+        P.pgo_set_state(h, s0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if label == "in_kernel":
+            done = P.pgo_iterate_until(h, max_sweeps, check, betas, GAMMA, tol)
+        else:
+            _, done, _ = P.pgo_solve(h, max_sweeps, check, GAMMA, tol, 1.0, betas.copy())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        out[label] = {"seconds": wall, "graphs_stopped": int(np.sum(done < max_sweeps)),
+                      "sweeps_median": float(np.median(done)), "sweeps_max": int(done.max()),
+                      "edge_iters_per_s": float(np.dot(done.astype(np.int64), edges_per_graph)) / wall}
+        out[label + "_sweeps"] = done
+    out["same_sweeps"] = bool(np.array_equal(out.pop("in_kernel_sweeps"), out.pop("host_loop_sweeps")))
+    P.pgo_destroy(h)
+    return out
+
+
 def cinit_leg(P, torch, cat, voff, eoff, steps):
     """Chordal initialisation of the whole batch on the device (FP64 CG per
     graph, tolerance 1e-10): wall time of the call, iterations, and the cost
@@ -416,6 +449,7 @@ def main():
     ap.add_argument("--skip-info", action="store_true", help="skip the information-model leg")
     ap.add_argument("--skip-ttt", action="store_true", help="skip the time-to-tolerance leg")
     ap.add_argument("--skip-adjoint", action="store_true", help="skip the differentiation leg")
+    ap.add_argument("--skip-stop", action="store_true", help="skip the stopping-rule leg")
     ap.add_argument("--no-tune", action="store_true", help="use --schedule/--block as given")
     ap.add_argument("--schedule", default="auto", choices=["auto", "phase", "graph"])
     ap.add_argument("--block", type=int, default=0)
@@ -545,6 +579,8 @@ def main():
         out["chordal_init"] = cinit_leg(P, torch, cat, voff, eoff, args.steps)
     if not args.skip_adjoint and args.steps:
         out["differentiation"] = adjoint_leg(P, torch)
+    if not args.skip_stop and args.steps:
+        out["stopping_rule"] = stopping_leg(P, torch, cat, voff, eoff, betas, epg)
     if not args.skip_ttt:
         F_star = reference_minimum()
         ttt = {"workload": "grid-1k", "F_star": F_star,

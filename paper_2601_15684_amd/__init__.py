@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
-    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_evaluate", "pgo_solve", "pgo_residuals", "pgo_get_poses",
+    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_evaluate", "pgo_iterate_until", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
     "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint", "pgo_chordal_init",
@@ -66,6 +66,7 @@ _SIGNATURES = {
     "pgo_cost": (C.c_int, [_P, _D]),
     "pgo_merit": (C.c_int, [_P, _D]),
     "pgo_evaluate": (C.c_int, [_P, _D, _D, _D]),
+    "pgo_iterate_until": (C.c_int, [_P, C.c_int32, C.c_int32, _D, C.c_double, C.c_double, _I32]),
     "pgo_solve": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, _D, _I32,
                             _I32]),
     "pgo_residuals": (C.c_int, [_P, _D]),
@@ -231,6 +232,17 @@ def pgo_evaluate(h):
     return F, res, mer
 
 
+def pgo_iterate_until(h, max_sweeps, check_every, beta, gamma, tol):
+    """Sweeps per graph until the residual e < tol (checked every check_every
+    sweeps) or max_sweeps; returns the sweeps each graph ran."""
+    G = pgo_info(h)["G"]
+    b = np.ascontiguousarray(np.broadcast_to(np.asarray(beta, np.float64), (G,)))
+    done = np.zeros(G, np.int32)
+    _chk(lib().pgo_iterate_until(h, int(max_sweeps), int(check_every), _dp(b), float(gamma),
+                                 float(tol), done.ctypes.data_as(C.POINTER(C.c_int32))))
+    return done
+
+
 def pgo_solve(h, max_sweeps, check_every, gamma, tol, beta_growth, beta):
     """Returns (beta reached, accepted sweeps, converged flags), one per graph."""
     G = pgo_info(h)["G"]
@@ -379,6 +391,9 @@ class PoseGraph:
 
     def evaluate(self):
         return pgo_evaluate(self.h)
+
+    def iterate_until(self, max_sweeps, check_every, beta, gamma, tol):
+        return pgo_iterate_until(self.h, max_sweeps, check_every, beta, gamma, tol)
 
     def solve(self, max_sweeps, check_every, gamma, beta, tol=0.0, beta_growth=2.0):
         return pgo_solve(self.h, max_sweeps, check_every, gamma, tol, beta_growth, beta)

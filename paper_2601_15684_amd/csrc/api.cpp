@@ -64,6 +64,7 @@ struct pgo_graph {
   std::vector<double> wbar_h;       // mean vertex weight of each graph (merit noise scale)
   double last_gamma = 1.0;
   int32_t* active_dev = nullptr;    // per-graph run flags (pgo_solve)
+  int32_t* done_dev = nullptr;      // per-graph sweeps run (pgo_iterate_until)
   int32_t* flag_dev = nullptr;      // per-graph restore flags (pgo_solve)
   void* snap[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   // differentiation
@@ -1097,6 +1098,70 @@ pgo_status pgo_iterate_graphs(pgo_graph* g, int32_t k, const double* beta, doubl
 pgo_status pgo_merit(pgo_graph* g, double* out) {
   if (!g || !out) return fail(PGO_EINVAL, "NULL argument");
   return pgo_evaluate(g, nullptr, nullptr, out);
+}
+
+pgo_status pgo_iterate_until(pgo_graph* g, int32_t max_sweeps, int32_t check_every,
+                             const double* beta, double gamma, double tol, int32_t* sweeps_done) {
+  if (!g || !beta || !sweeps_done) return fail(PGO_EINVAL, "NULL argument");
+  if (check_every < 1 || max_sweeps < 0 || max_sweeps % check_every != 0)
+    return fail(PGO_EINVAL, "need check_every >= 1 and max_sweeps a multiple of check_every");
+  if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
+  if (!std::isfinite(tol)) return fail(PGO_EINVAL, "tol must be finite");
+  const int32_t G = g->G;
+  for (int32_t j = 0; j < G; ++j)
+    if (!(std::isfinite(beta[j]) && beta[j] > 0.0))
+      return fail(PGO_EINVAL, "beta of graph " + std::to_string(j) + " must be finite and > 0");
+  pgo_status s = quaternion_only(g, "pgo_iterate_until");
+  if (s != PGO_OK) return s;
+  std::fill(sweeps_done, sweeps_done + G, 0);
+  if (max_sweeps == 0) return PGO_OK;
+  HIPCHK(hipSetDevice(g->device));
+  if (g->sched == PGO_SCHED_GRAPH) {  // the stopping rule inside the persistent kernel
+    if (!g->done_dev && (s = dalloc(g, &g->done_dev, size_t(G))) != PGO_OK) return s;
+    HIPCHK(hipMemcpyAsync(g->beta_dev, beta, sizeof(double) * G, hipMemcpyHostToDevice,
+                          g->stream));
+    SweepParams sp{beta[0], gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4, g->beta_dev,
+                   nullptr};
+    sp.tol = tol;
+    sp.check_every = check_every;
+    sp.done = g->done_dev;
+    const hipError_t he =
+        g->opt.precision == PGO_FP64
+            ? launch_graph_sweeps_stop<double>(view<double>(g), g->voff32, g->order, G,
+                                               max_sweeps, sp, g->block_graph, g->max_n,
+                                               g->graph_lds, g->stream)
+            : launch_graph_sweeps_stop<float>(view<float>(g), g->voff32, g->order, G,
+                                              max_sweeps, sp, g->block_graph, g->max_n,
+                                              g->graph_lds, g->stream);
+    if (he != hipSuccess) return hip_fail(he, "per-graph sweeps with stopping");
+    HIPCHK(hipMemcpyAsync(sweeps_done, g->done_dev, sizeof(int32_t) * G, hipMemcpyDeviceToHost,
+                          g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+  } else {  // chunks of check_every sweeps and an FP64 reduction after each
+    std::vector<int32_t> active(size_t(G), 1);
+    std::vector<double> r;
+    const int block = g->block_phase;
+    for (int32_t done = 0; done < max_sweeps; done += check_every) {
+      if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta,
+                            active.data())) != PGO_OK)
+        return s;
+      if ((s = reduce(g, r, false, g->active_dev)) != PGO_OK) return s;
+      bool any = false;
+      for (int32_t j = 0; j < G; ++j) {
+        if (!active[size_t(j)]) continue;
+        sweeps_done[j] += check_every;
+        const double* v = &r[size_t(kRedVals) * j];
+        const double e = (v[kDL2] + v[kDZ2]) / beta[j] + beta[j] * (v[kDQ2] + v[kDT2]);
+        if (e < tol) active[size_t(j)] = 0;
+        any = any || active[size_t(j)];
+      }
+      if (!any) break;
+    }
+  }
+  g->have_prev = true;
+  g->last_gamma = gamma;
+  g->beta_h.assign(beta, beta + G);
+  return PGO_OK;
 }
 
 pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, double gamma,

@@ -136,6 +136,12 @@ struct SweepParams {
   double beta, gamma, h1, h2, h3, h4;
   const double* beta_g;   // per-graph penalties (device, G values) or nullptr
   const int32_t* active;  // per-graph run flags (device, G values) or nullptr = all run
+  // stopping inside the per-graph kernel (launch_graph_sweeps_stop): every
+  // check_every sweeps a graph stops once its residual e is below tol and
+  // writes the sweeps it ran to done[graph]
+  double tol = 0.0;
+  int check_every = 0;
+  int32_t* done = nullptr;
 };
 
 // Device view for the rotation-matrix (chordal) model: the same edge order
@@ -183,6 +189,18 @@ template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
                                int G, int k, const SweepParams& sp, int block, int max_n, int lds,
                                hipStream_t st);
+// The per-graph kernel running up to k sweeps (k a multiple of
+// sp.check_every) with the stopping rule of App. E.1 evaluated in the
+// kernel: after every check_every sweeps a graph computes its residual
+// e = (|dlambda|^2 + |dz|^2)/beta + beta (|dq|^2 + |dt|^2) over the last
+// sweep (FP64 sums of the stored values) and stops when e < sp.tol;
+// sp.done[graph] receives the sweeps run.  Each check sweep ends with a
+// plain S and records the residual history, so the state equals that of
+// chunks of check_every sweeps run by separate calls.  block <= 1024.
+template <typename T>
+hipError_t launch_graph_sweeps_stop(const DevGraph<T>& g, const int32_t* voff,
+                                    const int32_t* order, int G, int k, const SweepParams& sp,
+                                    int block, int max_n, int lds, hipStream_t st);
 
 // Boundary preparation and state transfer (prep.hip), FP64.
 // Device-to-device copy as a kernel (4-byte aligned, size a multiple of 4).

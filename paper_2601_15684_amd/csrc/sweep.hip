@@ -51,6 +51,21 @@ __device__ __forceinline__ void acc4(Q4<A>& s, const Q4<A>& t) {
   s.w += t.w; s.x += t.x; s.y += t.y; s.z += t.z;
 }
 
+// squared distance of two stored vectors, in FP64
+template <typename T>
+__device__ __forceinline__ double sq4(const Q4<T>& a, const Q4<T>& b) {
+  const double w = double(a.w) - double(b.w), x = double(a.x) - double(b.x),
+               y = double(a.y) - double(b.y), z = double(a.z) - double(b.z);
+  return w * w + (x * x + y * y + z * z);
+}
+
+template <typename T>
+__device__ __forceinline__ double sq3(const V3<T>& a, const V3<T>& b) {
+  const double x = double(a.x) - double(b.x), y = double(a.y) - double(b.y),
+               z = double(a.z) - double(b.z);
+  return x * x + y * y + z * z;
+}
+
 template <typename A>
 __device__ __forceinline__ A l1(const Q4<A>& t) {
   return fabs(t.w) + fabs(t.x) + fabs(t.y) + fabs(t.z);
@@ -179,7 +194,8 @@ __device__ __forceinline__ void vertex_P(const DevGraph<T>& g, const State<T>& s
 
 template <typename T>
 __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const State<T>& st, int i,
-                                         const SweepParams& sp, bool save) {
+                                         const SweepParams& sp, bool save,
+                                         double* dsq = nullptr) {
   const Q4<T> pi = st.p(i), qi = st.q(i), li = st.lam(i);
   const V3<T> si = st.s(i);
   Q4<T> acc = {T(0), T(0), T(0), T(0)};
@@ -212,14 +228,20 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const State<T>& s
     g.q_prev[i] = qi;
     g.lam_prev[i] = li;
   }
-  st.q(i) = qn;
-  st.lam(i) = Q4<T>{li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x),
+  const Q4<T> ln = {li.w - gb * (pi.w - qn.w), li.x - gb * (pi.x - qn.x),
                     li.y - gb * (pi.y - qn.y), li.z - gb * (pi.z - qn.z)};
+  st.q(i) = qn;
+  st.lam(i) = ln;
+  if (dsq) {  // |dq|^2 and |dlambda|^2 of the stored values, FP64
+    dsq[0] += sq4(qn, qi);
+    dsq[1] += sq4(ln, li);
+  }
 }
 
 template <typename T>
 __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const State<T>& st, int i,
-                                         const SweepParams& sp, bool save) {
+                                         const SweepParams& sp, bool save,
+                                         double* dsq = nullptr) {
   V3<T> acc = {T(0), T(0), T(0)};
   struct InE {
     P4<T> u;
@@ -242,9 +264,11 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const State<T>& s
   const T b = T(sp.beta), h = T(sp.h3);
   const T a = g.cT[i] + b + h;
   if (save) g.t_prev[i] = ti;
-  st.t(i) = V3<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
-                  (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
-                  (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a};
+  const V3<T> tn = {(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
+                    (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
+                    (T(2) * acc.z + b * si.z + zi.z + h * ti.z) / a};
+  st.t(i) = tn;
+  if (dsq) dsq[2] += sq3(tn, ti);  // |dt|^2
 }
 
 // S update of vertex i; with po, the same pass over the out-edges also
@@ -255,7 +279,7 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, const State<T>& s
                                          const SweepParams& sp, bool save,
                                          POut<T>* po = nullptr, Q4<T>* p_out = nullptr,
                                          Q4<T>* q_out = nullptr, V3<T>* t_out = nullptr,
-                                         V3<T>* s_out = nullptr) {
+                                         V3<T>* s_out = nullptr, double* dsq = nullptr) {
   constexpr bool kF32 = sizeof(T) == 4;
   const Q4<T> pi = st.p(i), qi = st.q(i);
   const V3<T> ti = st.t(i), si = st.s(i);
@@ -286,7 +310,9 @@ __device__ __forceinline__ void vertex_S(const DevGraph<T>& g, const State<T>& s
     g.z_prev[i] = zi;
   }
   st.s(i) = sn;
-  st.z(i) = V3<T>{zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  const V3<T> zn = {zi.x - gb * (ti.x - sn.x), zi.y - gb * (ti.y - sn.y), zi.z - gb * (ti.z - sn.z)};
+  st.z(i) = zn;
+  if (dsq) dsq[3] += sq3(zn, zi);  // |dz|^2
   if (p_out) {
     *p_out = pi;
     *q_out = qi;
@@ -426,7 +452,122 @@ __global__ void __launch_bounds__(1024) k_graph_sweeps(DevGraph<T> g,
   }
 }
 
+// The per-graph kernel with the stopping rule evaluated inside it (see
+// launch_graph_sweeps_stop).  The four squared changes of a check sweep are
+// summed in FP64 per thread, then over the workgroup: wave shuffles, one
+// slot per wave, thread 0 adding the slots in order (deterministic).
+constexpr int kStopSlots = 80;  // 16 waves x 4 sums, and the decision
+
+__device__ __forceinline__ void block_sum4(double v[4], double* red) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int wave = int(threadIdx.x) / 64, nw = (int(blockDim.x) + 63) / 64;
+  if (threadIdx.x % 64 == 0)
+    for (int k = 0; k < 4; ++k) red[4 * wave + k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 4; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[4 * w + k];
+      v[k] = s;
+    }
+}
+
+template <int kSlots, typename T>
+__device__ __forceinline__ void graph_sweeps_stop(const DevGraph<T>& g, int gr, int v0, int v1,
+                                                  int k, const SweepParams& sp,
+                                                  unsigned char* lds, double* red) {
+  const State<T> st = state_load<kSlots>(g, v0, v1, lds);
+  const int C = sp.check_every;
+  for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<0, T>(g, st, i, sp, false);
+  __syncthreads();
+  int done = k;
+  for (int it = 0; it < k; ++it) {
+    const bool check = (it + 1) % C == 0;
+    // |dq|^2, |dlambda|^2, |dt|^2, |dz|^2 of this sweep (kept in registers:
+    // every sweep adds to them, a check sweep uses them)
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_Q(g, st, i, sp, check, d);
+    __syncthreads();
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) vertex_T(g, st, i, sp, check, d);
+    __syncthreads();
+    if (!check) {
+      for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<4, T>(g, st, i, sp, false);
+      __syncthreads();
+      continue;
+    }
+    // a check sweep ends with a plain S, as the last sweep of any launch
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x)
+      vertex_S<T>(g, st, i, sp, true, nullptr, nullptr, nullptr, nullptr, nullptr, d);
+    block_sum4(d, red);
+    if (threadIdx.x == 0) {
+      const double e = (d[1] + d[3]) / sp.beta + sp.beta * (d[0] + d[2]);
+      red[kStopSlots - 1] = (e < sp.tol || it + 1 == k) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const bool stop = red[kStopSlots - 1] != 0.0;
+    __syncthreads();  // the decision is read before the slots are reused
+    if (stop) {
+      done = it + 1;
+      break;
+    }
+    for (int i = v0 + threadIdx.x; i < v1; i += blockDim.x) phase<0, T>(g, st, i, sp, false);
+    __syncthreads();
+  }
+  state_store<kSlots>(g, st, v0, v1);
+  if (threadIdx.x == 0) sp.done[gr] = done;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024) k_graph_sweeps_stop(DevGraph<T> g,
+                                                            const int32_t* __restrict__ voff,
+                                                            const int32_t* __restrict__ order,
+                                                            int k, SweepParams sp, int lds_bytes) {
+  extern __shared__ unsigned char lds_raw[];
+  const int gr = order[blockIdx.x];
+  const int v0 = voff[gr], v1 = voff[gr + 1];
+  if (sp.active && !sp.active[gr]) {
+    if (threadIdx.x == 0) sp.done[gr] = 0;
+    return;
+  }
+  if (sp.beta_g) sp.beta = sp.beta_g[gr];
+  double* red = reinterpret_cast<double*>(lds_raw);
+  unsigned char* lds = lds_raw + sizeof(double) * kStopSlots;
+  const size_t budget = size_t(lds_bytes) - sizeof(double) * kStopSlots;
+  const size_t n = size_t(v1 - v0);
+  int slots = 0;
+  while (slots < 6 && state_lds_bytes<T>(slots + 1, n) <= budget) ++slots;
+  switch (slots) {
+    case 6: graph_sweeps_stop<6, T>(g, gr, v0, v1, k, sp, lds, red); break;
+    case 5: graph_sweeps_stop<5, T>(g, gr, v0, v1, k, sp, lds, red); break;
+    case 4: graph_sweeps_stop<4, T>(g, gr, v0, v1, k, sp, lds, red); break;
+    case 3: graph_sweeps_stop<3, T>(g, gr, v0, v1, k, sp, lds, red); break;
+    case 2: graph_sweeps_stop<2, T>(g, gr, v0, v1, k, sp, lds, red); break;
+    case 1: graph_sweeps_stop<1, T>(g, gr, v0, v1, k, sp, lds, red); break;
+    default: graph_sweeps_stop<0, T>(g, gr, v0, v1, k, sp, lds, red); break;
+  }
+}
+
 constexpr size_t kLdsBytes = 160 * 1024;
+
+template <typename T>
+hipError_t launch_graph_sweeps_stop(const DevGraph<T>& g, const int32_t* voff,
+                                    const int32_t* order, int G, int k, const SweepParams& sp,
+                                    int block, int max_n, int lds, hipStream_t st) {
+  if (G <= 0 || k <= 0) return hipSuccess;
+  if (block <= 0 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  if (sp.check_every < 1 || k % sp.check_every || !sp.done) return hipErrorInvalidValue;
+  const size_t red = sizeof(double) * kStopSlots;
+  const size_t bytes =
+      lds ? std::min(kLdsBytes, red + state_lds_bytes<T>(6, size_t(max_n))) : red;
+  if (hipFuncSetAttribute(reinterpret_cast<const void*>(&k_graph_sweeps_stop<T>),
+                          hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)) != hipSuccess)
+    return hipGetLastError();
+  hipLaunchKernelGGL((k_graph_sweeps_stop<T>), dim3(G), dim3(block), bytes, st, g, voff, order, k,
+                     sp, int(bytes));
+  return hipGetLastError();
+}
 
 template <typename T>
 hipError_t launch_graph_sweeps(const DevGraph<T>& g, const int32_t* voff, const int32_t* order,
@@ -457,5 +598,11 @@ template hipError_t launch_graph_sweeps<float>(const DevGraph<float>&, const int
 template hipError_t launch_graph_sweeps<double>(const DevGraph<double>&, const int32_t*,
                                                 const int32_t*, int, int, const SweepParams&, int,
                                                 int, int, hipStream_t);
+template hipError_t launch_graph_sweeps_stop<float>(const DevGraph<float>&, const int32_t*,
+                                                    const int32_t*, int, int, const SweepParams&,
+                                                    int, int, int, hipStream_t);
+template hipError_t launch_graph_sweeps_stop<double>(const DevGraph<double>&, const int32_t*,
+                                                     const int32_t*, int, int, const SweepParams&,
+                                                     int, int, int, hipStream_t);
 
 }  // namespace pgo

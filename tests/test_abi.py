@@ -101,7 +101,9 @@ def test_null_handle_calls(pgo):
     # every reduction entry point refuses a null handle before touching a device
     for call in (lambda: lib.pgo_cost(None, buf), lambda: lib.pgo_residuals(None, buf),
                  lambda: lib.pgo_merit(None, buf), lambda: lib.pgo_evaluate(None, buf, buf, buf),
-                 lambda: lib.pgo_evaluate(None, None, None, None)):
+                 lambda: lib.pgo_evaluate(None, None, None, None),
+                 lambda: lib.pgo_iterate_until(None, 20, 10, buf, 1.4, 1e-3,
+                                               (C.c_int32 * 8)())):
         assert call() == 1  # PGO_EINVAL
     pgo.pgo_destroy(None)
 

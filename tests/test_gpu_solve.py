@@ -140,3 +140,33 @@ def test_evaluate_equals_the_three_calls(pgo, prec):
         assert np.array_equal(F, h.cost())
         assert np.array_equal(res, h.residuals())
         assert np.array_equal(mer, h.merit())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_stopping_inside_the_kernel_equals_the_host_loop(pgo, prec):
+    """pgo_iterate_until in the per-graph schedule (the stopping rule e < tol
+    evaluated inside the persistent kernel) stops every graph after the same
+    number of sweeps as the host-checked loops (the per-phase schedule, and
+    pgo_solve without penalty control), with the same bits."""
+    b = S.batched(4096, first=200, count=12)
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs])
+    with pgo.PoseGraph.from_batch(b, precision=prec, schedule="graph") as h:
+        h.iterate(200, betas, GAMMA)
+        e200 = h.residuals()[:, 2]
+    tol = float(np.median(e200))   # about half of the graphs stop before 200 sweeps
+    runs = {}
+    for label, sched in (("kernel", "graph"), ("host", "phase")):
+        with pgo.PoseGraph.from_batch(b, precision=prec, schedule=sched) as h:
+            done = h.iterate_until(400, 20, betas, GAMMA, tol)
+            runs[label] = (done, h.state(), h.residuals())
+    with pgo.PoseGraph.from_batch(b, precision=prec, schedule="graph") as h:
+        beta_out, done_solve, conv = h.solve(400, 20, GAMMA, betas.copy(), tol=tol, beta_growth=1.0)
+        runs["solve"] = (done_solve, h.state(), None)
+    assert np.array_equal(runs["kernel"][0], runs["host"][0]), (runs["kernel"][0], runs["host"][0])
+    assert np.array_equal(runs["kernel"][0], runs["solve"][0])
+    assert np.array_equal(runs["kernel"][1], runs["host"][1])
+    assert np.array_equal(runs["kernel"][1], runs["solve"][1])
+    done, _, res = runs["kernel"]
+    stopped = done < 400
+    assert stopped.any() and np.all(res[stopped, 2] < tol) and np.all(done % 20 == 0)
+    assert np.all(conv[stopped] == 1)
