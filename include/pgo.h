@@ -223,14 +223,13 @@ pgo_status pgo_evaluate(pgo_graph* g, double* F, double* res, double* merit);
  * beta (host array, G values > 0) and stops after the first chunk whose
  * last sweep leaves the residual e of App. E.1 below tol (see
  * pgo_residuals [2]), or after max_sweeps sweeps (a multiple of
- * check_every).  In the per-graph schedule the whole call is one launch and
- * each graph evaluates e inside it (FP64 sums of the stored values), with no
- * host round trip per chunk; otherwise the chunks are separate launches
- * checked on the host.  The state equals that of the same chunks run by
- * pgo_iterate_graphs calls.
+ * check_every).  For the quaternion model in the per-graph schedule the
+ * whole call is one launch and each graph evaluates e inside it (FP64 sums
+ * of the stored values), with no host round trip per chunk; otherwise the
+ * chunks are separate launches checked on the host.  The state equals that
+ * of the same chunks run by pgo_iterate_graphs calls.
  *   sweeps_done  out, G values: the sweeps each graph ran
- * Isotropic quaternion model only (PGO_ESTATE otherwise).  Synchronises the
- * stream.
+ * Synchronises the stream.
  */
 pgo_status pgo_iterate_until(pgo_graph* g, int32_t max_sweeps, int32_t check_every,
                              const double* beta, double gamma, double tol, int32_t* sweeps_done);

@@ -1111,12 +1111,11 @@ pgo_status pgo_iterate_until(pgo_graph* g, int32_t max_sweeps, int32_t check_eve
   for (int32_t j = 0; j < G; ++j)
     if (!(std::isfinite(beta[j]) && beta[j] > 0.0))
       return fail(PGO_EINVAL, "beta of graph " + std::to_string(j) + " must be finite and > 0");
-  pgo_status s = quaternion_only(g, "pgo_iterate_until");
-  if (s != PGO_OK) return s;
+  pgo_status s = PGO_OK;
   std::fill(sweeps_done, sweeps_done + G, 0);
   if (max_sweeps == 0) return PGO_OK;
   HIPCHK(hipSetDevice(g->device));
-  if (g->sched == PGO_SCHED_GRAPH) {  // the stopping rule inside the persistent kernel
+  if (g->sched == PGO_SCHED_GRAPH && !g->chordal && !g->aniso) {  // the rule inside the kernel
     if (!g->done_dev && (s = dalloc(g, &g->done_dev, size_t(G))) != PGO_OK) return s;
     HIPCHK(hipMemcpyAsync(g->beta_dev, beta, sizeof(double) * G, hipMemcpyHostToDevice,
                           g->stream));
@@ -1140,7 +1139,7 @@ pgo_status pgo_iterate_until(pgo_graph* g, int32_t max_sweeps, int32_t check_eve
   } else {  // chunks of check_every sweeps and an FP64 reduction after each
     std::vector<int32_t> active(size_t(G), 1);
     std::vector<double> r;
-    const int block = g->block_phase;
+    const int block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
     for (int32_t done = 0; done < max_sweeps; done += check_every) {
       if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta,
                             active.data())) != PGO_OK)

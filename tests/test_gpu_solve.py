@@ -170,3 +170,32 @@ def test_stopping_inside_the_kernel_equals_the_host_loop(pgo, prec):
     stopped = done < 400
     assert stopped.any() and np.all(res[stopped, 2] < tol) and np.all(done % 20 == 0)
     assert np.all(conv[stopped] == 1)
+
+
+@pytest.mark.parametrize("model", ["chordal", "info"])
+def test_stopping_rule_of_the_other_models(pgo, model):
+    """pgo_iterate_until for the chordal and information models (chunks
+    checked on the host) stops each graph where pgo_solve without penalty
+    control does, with the same bits."""
+    b = S.batched(4096, first=300, count=6)
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs])
+    kw = dict(precision="fp32", schedule="graph")
+    info = None
+    if model == "info":
+        info = np.concatenate([S.random_info(gr.m, gr.tau, 10.0, seed=k) for k, gr in enumerate(b.graphs)])
+    else:
+        kw["model"] = model
+
+    def make():
+        return pgo.PoseGraph.from_batch(b, info=info, **kw)
+
+    with make() as h:
+        h.iterate(100, betas, GAMMA)
+        tol = float(np.median(h.residuals()[:, 2]))
+    with make() as h:
+        done = h.iterate_until(300, 20, betas, GAMMA, tol)
+        state = h.state()
+    with make() as h:
+        _, done_solve, _ = h.solve(300, 20, GAMMA, betas.copy(), tol=tol, beta_growth=1.0)
+        assert np.array_equal(done, done_solve) and np.array_equal(state, h.state())
+    assert (done < 300).any()
