@@ -69,7 +69,7 @@ def abar(g):
 
 
 KERNEL_SOURCES = {  # device sources each profiled sweep kernel is built from
-    "k_graph_sweeps<float>": ("sweep.hip", "qmath.hpp", "internal.hpp"),
+    "k_graph_sweeps<float>": ("sweep_graph.hip", "sweep_core.hpp", "qmath.hpp", "internal.hpp"),
     "k_graph_sweeps_c<float>": ("chordal.hip", "polar.hpp", "qmath.hpp", "internal.hpp"),
     "k_graph_sweeps_a<float>": ("aniso.hip", "qmath.hpp", "internal.hpp"),
 }

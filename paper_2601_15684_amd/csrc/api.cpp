@@ -83,6 +83,7 @@ struct pgo_graph {
   void *o_tt = nullptr, *o_w = nullptr, *i_tt = nullptr, *i_w = nullptr;
   void *cQ = nullptr, *cT = nullptr, *cS = nullptr;
   void *p = nullptr, *q = nullptr, *lam = nullptr, *t = nullptr, *s = nullptr, *z = nullptr;
+  void *xy = nullptr, *xm = nullptr;  // sweep scratch slot (quaternion models)
   void *q_prev = nullptr, *lam_prev = nullptr, *t_prev = nullptr, *s_prev = nullptr,
        *z_prev = nullptr;
   int32_t *ei = nullptr, *ej = nullptr;
@@ -167,6 +168,8 @@ DevGraph<T> view(const pgo_graph* g) {
   d.t = static_cast<V3<T>*>(g->t);
   d.s = static_cast<V3<T>*>(g->s);
   d.z = static_cast<V3<T>*>(g->z);
+  d.xy = static_cast<Q4<T>*>(g->xy);
+  d.xm = static_cast<T*>(g->xm);
   d.q_prev = static_cast<Q4<T>*>(g->q_prev);
   d.lam_prev = static_cast<Q4<T>*>(g->lam_prev);
   d.t_prev = static_cast<V3<T>*>(g->t_prev);
@@ -330,6 +333,10 @@ pgo_status alloc_precision(pgo_graph* g) {
   void** ew[] = {&g->o_w, &g->i_w};
   for (void** v : ew)
     if ((s = dalloc_bytes(g, v, rw * sizeof(T) * m)) != PGO_OK) return s;
+  if (!g->chordal) {
+    if ((s = dalloc_bytes(g, &g->xy, 4 * sizeof(T) * n)) != PGO_OK) return s;
+    if ((s = dalloc_bytes(g, &g->xm, sizeof(T) * n)) != PGO_OK) return s;
+  }
   void** c1[] = {&g->cQ, &g->cT, &g->cS};
   for (void** v : c1)
     if ((s = dalloc_bytes(g, v, sizeof(T) * n)) != PGO_OK) return s;

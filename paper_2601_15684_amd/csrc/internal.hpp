@@ -42,6 +42,11 @@ struct DevGraph {
   V3<T>* t;
   V3<T>* s;
   V3<T>* z;
+  // per-vertex slot between phases of the sweep (scratch): P's in-edge sum
+  // from T to S+P, then the tau part of Q's out-edge sum from S+P to Q, and
+  // the magnitude of the in-edge terms (FP32 cancellation check)
+  Q4<T>* xy;
+  T* xm;
   // values before the last sweep of an iterate call (residual history)
   Q4<T>* q_prev;
   Q4<T>* lam_prev;

@@ -30,3 +30,18 @@ def pgo():
     import paper_2601_15684_amd as P
     P.lib()
     return P
+
+
+def pytest_terminal_summary(terminalreporter):
+    """The raw parity errors of every GPU comparison and their bounds
+    (tests/tolerance.py); also written to $PGO_PARITY_REPORT when set."""
+    import sys as _sys
+    T = _sys.modules.get("tests.tolerance")
+    if T is None or not T.REPORT:
+        return
+    text = T.format_report()
+    terminalreporter.write_line(text)
+    path = os.environ.get("PGO_PARITY_REPORT")
+    if path:
+        with open(path, "w") as f:
+            f.write(text + "\n")

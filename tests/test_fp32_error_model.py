@@ -1,15 +1,26 @@
-"""The FP32 tolerance of the GPU parity tests is the arithmetic's, not the
-kernels': the FP64 oracle itself, evaluated in float32 (same formulas, every
-tensor float32), departs from its float64 run after 10 sweeps by an amount
-that grows with the coordinate magnitude, and stays within the scaled bound
-1e-4 * max(1, max|t| / 10 m) used for the GPU FP32 path."""
+"""What float32 arithmetic costs on the parity workloads, on the CPU: the
+FP64 oracle itself run in float32 (the same formulas, every tensor float32;
+tests/tolerance.py) against its float64 run after 10 sweeps, per block.
+
+  * On the 100-pose circle and the 1000-pose grid the float32 oracle stays
+    within 2.5e-5 of the float64 one, so the GPU FP32 path is held to the
+    plain 1e-4 there.
+  * On the sphere (2500 poses, coordinates drifting to ~180 m along its
+    odometry chain) and the 100k-pose grid (~430 m) it departs by more than
+    1e-4 in some block: no FP32 arithmetic meets 1e-4 on those inputs, and
+    the GPU is held to 8x the float32 oracle's own departure.
+  * The order in which the edge terms are added alone moves that departure
+    by more than 2x on the sphere (edges as given against shuffled), which
+    is why the floor is the larger of two orders and carries a factor.
+"""
 import numpy as np
 import pytest
-import torch
 
 import pgo_synth as S
+from oracle import chordal as C
 from oracle import prep
 from oracle import pradmm as O
+from tests import tolerance as T
 
 
 def abar(g):
@@ -19,55 +30,59 @@ def abar(g):
     return float(d.mean())
 
 
-def run_in(monkeypatch, P, st, beta, k, dtype):
-    monkeypatch.setattr(O, "F64", dtype)
-    monkeypatch.setattr(O, "D4", O.D4.to(dtype))
-    monkeypatch.setattr(O, "ONE", O.ONE.to(dtype))
-    Pd = {key: (v.to(dtype) if torch.is_tensor(v) and v.is_floating_point() else v) for key, v in P.items()}
-    s = {key: v.to(dtype) for key, v in st.items()}
-    for _ in range(k):
-        s = O.sweep(Pd, s, beta, 1.4)
-    monkeypatch.undo()
-    return {key: v.double() for key, v in s.items()}
-
-
-@pytest.mark.parametrize("name", ["grid-1k", "sphere-2.5k"])
-def test_float32_oracle_error_scales_with_coordinates(monkeypatch, name):
+def quat_case(name, gamma=1.4):
     g = S.make_config(name)
     beta = 0.01 * abar(g)
     P, p0, t0 = prep.prepare_graph(g)
-    st0 = O.init_state(p0, t0)
-    ref = O.iterate(P, st0, 10, beta, 1.4)
-    lo = run_in(monkeypatch, P, st0, beta, 10, torch.float32)
-    L = max(1.0, float(ref["t"].abs().max()) / 10.0)
-    err = {k: float((lo[k] - ref[k]).abs().max()) / (beta if k in ("lam", "z") else 1.0) for k in ref}
-    worst = max(err.values())
-    assert worst <= 1e-4 * L            # within the scaled bound
-    assert worst >= 1e-7 * L            # and not trivially: the bound is ~the arithmetic's error
-    # the error is proportional to the coordinate scale, not an absolute floor
-    assert err["t"] >= 1e-8 * float(ref["t"].abs().max())
+    return P, O.init_state(p0, t0), beta, gamma
 
 
-@pytest.mark.parametrize("name", ["grid-1k", "sphere-2.5k", "grid-100k"])
-def test_float32_chordal_oracle_error_scales_with_coordinates(name):
-    """The same bound for the rotation-matrix rendering: its oracle run with
-    every tensor in float32 (the polar factor's SVD included) stays within
-    1e-4 L of its float64 run after 10 sweeps in P, Q, t, s, and not
-    trivially so.  The multipliers sum every sweep's rounded P - Q and
-    t - s; on the 100k-pose grid Lambda/beta departs by ~1.6e-4 L, so the
-    multiplier bound is 1e-3 L."""
-    from oracle import chordal as C
+@pytest.mark.parametrize("name", ["circle-100", "grid-1k"])
+def test_float32_oracle_meets_1e4_on_small_workloads(name):
+    P, st0, beta, gamma = quat_case(name)
+    floor = T.quat_floor(P, st0, beta, gamma, 10)
+    assert max(floor.values()) <= 2.5e-5, floor      # so the GPU bound is the plain 1e-4
+    assert max(floor.values()) >= 1e-7, floor        # and float32 is not trivially exact here
+    assert T.fp32_bounds(floor) == {k: T.FP32_TOL for k in floor}
+
+
+@pytest.mark.parametrize("gamma", [1.4, 1.5, 1.9])
+def test_float32_oracle_exceeds_1e4_on_the_sphere(gamma):
+    P, st0, beta, gamma = quat_case("sphere-2.5k", gamma)
+    floor = T.quat_floor(P, st0, beta, gamma, 10)
+    assert max(floor.values()) > 1e-4, floor
+    assert max(floor.values()) < 1e-2, floor         # float32-sized, not a broken run
+
+
+def test_summation_order_spread_on_the_sphere():
+    """The float32 oracle with the edges as given and in three shuffled
+    orders: the departures differ by more than 2x in some block, and half
+    the bound (the larger of two orders' departures, times 8, halved) still
+    covers every order's departure."""
+    P, st0, beta, gamma = quat_case("sphere-2.5k")
+    ref = T.pack_quat(O.iterate(P, st0, 10, beta, gamma))
+    deps = [T.quat_departure(P, st0, beta, gamma, 10, ref)]
+    deps += [T.quat_departure(T._permuted(P, seed), st0, beta, gamma, 10, ref) for seed in (2, 3, 4)]
+    spread = {k: max(d[k] for d in deps) / min(d[k] for d in deps) for k in deps[0]}
+    assert max(spread.values()) > 2.0, spread
+    bounds = T.fp32_bounds(T.quat_floor(P, st0, beta, gamma, 10, ref=ref))
+    for d in deps:
+        assert all(d[k] <= bounds[k] / 2 for k in d), (d, bounds)
+
+
+@pytest.mark.slow
+def test_float32_oracle_exceeds_1e4_on_grid_100k():
+    P, st0, beta, gamma = quat_case("grid-100k")
+    floor = T.quat_floor(P, st0, beta, gamma, 10)
+    assert max(floor.values()) > 1e-4, floor
+
+
+@pytest.mark.parametrize("name", ["circle-100", "grid-1k"])
+def test_float32_chordal_oracle_meets_1e4_on_small_workloads(name):
+    """The rotation-matrix rendering's oracle in float32 stays within 2.5e-5
+    on the circle and the 1000-pose grid (the GPU bound is the plain 1e-4)."""
     g = S.make_config(name)
     beta = 0.01 * abar(g)
     Pb, P0, t0 = C.prepare_graph(g)
-    st0 = C.init_state(P0, t0)
-    ref = C.iterate(Pb, st0, 10, beta, 1.4)
-    P32 = {k: (v.float() if torch.is_tensor(v) and v.is_floating_point() else v) for k, v in Pb.items()}
-    lo = C.iterate(P32, {k: v.float() for k, v in st0.items()}, 10, beta, 1.4)
-    L = max(1.0, float(ref["t"].abs().max()) / 10.0)
-    err = {k: float((lo[k].double() - ref[k]).abs().max()) / (beta if k in ("L", "z") else 1.0)
-           for k in ref}
-    worst = max(err.values())
-    assert max(err[k] for k in ("P", "Q", "t", "s")) <= 1e-4 * L, err
-    assert max(err["L"], err["z"]) <= 1e-3 * L, err
-    assert worst >= 1e-7 * L
+    floor = T.chordal_floor(Pb, C.init_state(P0, t0), beta, 1.4, 10)
+    assert max(floor.values()) <= 2.5e-5, floor

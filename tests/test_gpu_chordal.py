@@ -2,18 +2,17 @@
 HIP library with PGO_MODEL_CHORDAL, through its C ABI, against the FP64 CPU
 oracle of oracle/chordal.py on the same seeded inputs.
 
-Tolerances and scaling are those of the quaternion tests: FP64 1e-10 and
-FP32 1e-4 max-abs on the state after 10 sweeps, multipliers as Lambda/beta
-and z/beta, every block divided by L = max(1, max|t| / 10 m) (the FP32
-error grows with the coordinate magnitude; tests/test_fp32_error_model.py
-pins that for this model's oracle in float32 too, and the looser 1e-3 L
-for the multipliers of the 100k-pose grid)."""
+Tolerances are those of the quaternion tests (tests/tolerance.py): the
+state after 10 sweeps, max-abs per block (P, Q, t, s, Lambda/beta, z/beta),
+unscaled; FP64 1e-10, FP32 max(1e-4, 4 x the departure of this model's
+oracle run in float32 from its float64 run on the same input)."""
 import numpy as np
 import pytest
 import torch
 
 import pgo_synth as S
 from oracle import chordal as C
+from tests import tolerance as T
 
 pytestmark = pytest.mark.gpu
 
@@ -48,20 +47,16 @@ def oracle_run(g, k, beta, gamma=GAMMA, st=None):
     return Pb, st, prev
 
 
-def scaled_err(a, b, beta):
-    L = max(1.0, float(np.abs(b[:, 18:21]).max()) / 10.0) if b.shape[0] else 1.0
-    out = {}
-    for k, s in SL.items():
-        d = float(np.abs(a[:, s] - b[:, s]).max()) if a.shape[0] else 0.0
-        if k in ("L", "z"):
-            d /= beta
-        out[k] = d / L
-    return out
+def floor(g, k, beta, ref, prec, gamma=GAMMA):
+    """What the arithmetic costs on this input (tests/tolerance.py)."""
+    Pb, P0, t0 = C.prepare_graph(g)
+    return T.chordal_floor(Pb, C.init_state(P0, t0), beta, gamma, k, ref=ref,
+                           dtype=torch.float64 if prec == "fp64" else torch.float32)
 
 
-def assert_parity(errs, tol, label=""):
-    bad = {k: v for k, v in errs.items() if not v <= tol}
-    assert not bad, f"{label} exceeds {tol}: {bad}"
+def check(label, prec, got, ref, beta, floor=None):
+    T.assert_within("chordal " + label, prec, T.block_errors(got, ref, beta, T.CHORDAL_BLOCKS),
+                    floor)
 
 
 def chordal(pgo, g, **opt):
@@ -91,7 +86,8 @@ def test_fp64_state_parity_10_sweeps(pgo, name, sched):
     beta = 0.01 * abar(g)
     _, st, _ = oracle_run(g, 10, beta)
     got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp64", schedule=sched)
-    assert_parity(scaled_err(got, pack(st), beta), 1e-10, f"{name}/{sched}")
+    ref = pack(st)
+    check(f"{name}/{sched}", "fp64", got, ref, beta, floor(g, 10, beta, ref, "fp64"))
 
 
 @pytest.mark.parametrize("name", ["circle-100", "grid-1k", "sphere-2.5k"])
@@ -99,9 +95,11 @@ def test_fp32_state_parity_10_sweeps(pgo, name):
     g = S.make_config(name)
     beta = 0.01 * abar(g)
     _, st, _ = oracle_run(g, 10, beta)
+    ref = pack(st)
+    f32 = floor(g, 10, beta, ref, "fp32")
     for sched in ("phase", "graph"):
         got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp32", schedule=sched)
-        assert_parity(scaled_err(got, pack(st), beta), 1e-4, f"{name}/fp32/{sched}")
+        check(f"{name}/{sched}", "fp32", got, ref, beta, f32)
 
 
 def test_edge_cases_fp64(pgo):
@@ -129,7 +127,7 @@ def test_edge_cases_fp64(pgo):
         for sched in ("phase", "graph"):
             for block in (64, 256):
                 got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp64", schedule=sched, block=block)
-                assert_parity(scaled_err(got, pack(st), beta), 1e-10, f"{label}/{sched}/{block}")
+                check(f"{label}/{sched}/{block}", "fp64", got, pack(st), beta)
 
 
 def test_schedules_and_block_sizes_bitwise_identical(pgo):
@@ -160,7 +158,8 @@ def test_batched_equals_single_and_oracle(pgo):
             assert costs[k] == F
             if prec == "fp64":
                 _, st, _ = oracle_run(gr, 8, betas[k])
-                assert_parity(scaled_err(got, pack(st), betas[k]), 1e-10, gr.name)
+                ref = pack(st)
+                check(gr.name, "fp64", got, ref, betas[k], floor(gr, 8, betas[k], ref, "fp64"))
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -212,7 +211,8 @@ def test_noise_free_fixed_point(pgo):
         with chordal(pgo, g, precision=prec) as h:
             s0 = h.state()
             h.iterate(5, beta, GAMMA)
-            assert_parity(scaled_err(h.state(), s0, beta), tol, prec)
+            err = T.block_errors(h.state(), s0, beta, T.CHORDAL_BLOCKS)
+            assert max(err.values()) <= tol, (prec, err)
 
 
 def test_fp32_polar_island(pgo):
@@ -254,24 +254,20 @@ def test_fp32_polar_island(pgo):
         h.iterate(1, beta, GAMMA)
         got = h.state()
     assert np.abs(got[:, 0:9] - ref[:, 0:9]).max() < 1e-6
-    assert_parity(scaled_err(got, ref, beta), 1e-4, "island")
+    check("grid-1k/polar island", "fp32", got, ref, beta)
 
 
 def test_full_size_grid_100k_parity(pgo):
-    """The 100k-pose grid in the per-phase schedule.  FP32: the multipliers
-    carry the accumulated rounding of every sweep's P - Q and t - s, and on
-    this grid the oracle's own float32 run already departs by 1.6e-4 L in
-    Lambda/beta, so they get 1e-3 L (pinned in the FP32 error-model test)."""
+    """The 100k-pose grid in the per-phase schedule, FP64 and FP32 (the
+    multipliers carry the accumulated rounding of every sweep's P - Q and
+    t - s; the float32 oracle's own departure sets their bound)."""
     g = S.make_config("grid-100k")
     beta = 0.01 * abar(g)
     _, st, _ = oracle_run(g, 10, beta)
     ref = pack(st)
-    got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp64", schedule="phase")
-    assert_parity(scaled_err(got, ref, beta), 1e-10, "grid-100k/fp64")
-    got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp32", schedule="phase")
-    err = scaled_err(got, ref, beta)
-    assert_parity({k: v for k, v in err.items() if k not in ("L", "z")}, 1e-4, "grid-100k/fp32")
-    assert_parity({k: err[k] for k in ("L", "z")}, 1e-3, "grid-100k/fp32 multipliers")
+    for prec in ("fp64", "fp32"):
+        got, _, _ = gpu_run(pgo, g, 10, beta, precision=prec, schedule="phase")
+        check("grid-100k/phase", prec, got, ref, beta, floor(g, 10, beta, ref, prec))
 
 
 def test_solve_and_quaternion_only_calls(pgo):
