@@ -218,6 +218,34 @@ pgo_status pgo_merit(pgo_graph* g, double* out);
 pgo_status pgo_evaluate(pgo_graph* g, double* F, double* res, double* merit);
 
 /*
+ * pgo_evaluate_noalloc -- pgo_evaluate for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same FP64 reductions, with their
+ * partial sums and per-graph values in a static device array of the library
+ * (2 MiB on each device it runs on, held until the process ends) instead of
+ * the handle's buffers, and every result written on the device.  No
+ * allocation, no host transfer and no synchronisation: the work is enqueued
+ * on the handle's stream.
+ *   beta_dev  in, device, G doubles: each graph's penalty (pgo_evaluate uses
+ *             those of the last iterate call)
+ *   gamma     the relaxation step of the merit (pgo_evaluate uses the last
+ *             iterate call's)
+ *   out_dev   out, device, G x 8 doubles per graph: F, the five residuals of
+ *             pgo_residuals [0..4], L_beta and Psi of pgo_merit -- equal bit
+ *             for bit to what pgo_evaluate returns for the same penalties
+ * Quaternion models (PGO_MODEL_QUAT, PGO_MODEL_QUAT_INFO) only
+ * (PGO_ESTATE otherwise).  PGO_EINVAL when the handle's reductions need more
+ * of the array than it holds (2 per edge chunk + 9 per vertex chunk + 11 per
+ * graph doubles, chunks of up to 8192 items per graph; the 4096-graph batch
+ * needs about a third of it).  The array is shared by every call on one
+ * device and keeps the last call's contents (each call writes all it
+ * reads); calls that overlap on one device race on it.  Non-finite values
+ * are returned as they are (no PGO_ENUMERIC).
+ */
+pgo_status pgo_evaluate_noalloc(pgo_graph* g, const double* beta_dev, double gamma,
+                                double* out_dev);
+
+/*
  * pgo_iterate_until -- sweeps with the experiments' stopping rule and no
  * penalty control: every graph runs chunks of check_every sweeps at its
  * beta (host array, G values > 0) and stops after the first chunk whose

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "PgoError", "PgoOptions", "lib", "pgo_default_options", "pgo_create", "pgo_create_batched",
-    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_evaluate", "pgo_iterate_until", "pgo_solve", "pgo_residuals", "pgo_get_poses",
+    "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_evaluate", "pgo_evaluate_noalloc", "pgo_iterate_until", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
     "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint", "pgo_chordal_init",
@@ -66,6 +66,7 @@ _SIGNATURES = {
     "pgo_cost": (C.c_int, [_P, _D]),
     "pgo_merit": (C.c_int, [_P, _D]),
     "pgo_evaluate": (C.c_int, [_P, _D, _D, _D]),
+    "pgo_evaluate_noalloc": (C.c_int, [_P, _P, C.c_double, _P]),
     "pgo_iterate_until": (C.c_int, [_P, C.c_int32, C.c_int32, _D, C.c_double, C.c_double, _I32]),
     "pgo_solve": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_double, _D, _I32,
                             _I32]),
@@ -230,6 +231,14 @@ def pgo_evaluate(h):
     F, res, mer = np.empty(G), np.empty((G, 6)), np.empty((G, 2))
     _chk(lib().pgo_evaluate(h, _dp(F), _dp(res), _dp(mer)))
     return F, res, mer
+
+
+def pgo_evaluate_noalloc(h, beta_dev, gamma, out_dev):
+    """The reductions of pgo_evaluate into a device buffer without allocating:
+    beta_dev (G float64) and out_dev (G x 8 float64) are device pointers
+    (e.g. a torch tensor's data_ptr()); enqueued on the handle's stream."""
+    _chk(lib().pgo_evaluate_noalloc(h, C.c_void_p(int(beta_dev)), float(gamma),
+                                    C.c_void_p(int(out_dev))))
 
 
 def pgo_iterate_until(h, max_sweeps, check_every, beta, gamma, tol):

@@ -1292,6 +1292,36 @@ pgo_status pgo_evaluate(pgo_graph* g, double* F, double* res, double* merit) {
   return PGO_OK;
 }
 
+pgo_status pgo_evaluate_noalloc(pgo_graph* g, const double* beta_dev, double gamma,
+                                double* out_dev) {
+  if (!g || !beta_dev || !out_dev) return fail(PGO_EINVAL, "NULL argument");
+  if (g->chordal)
+    return fail(PGO_ESTATE, "pgo_evaluate_noalloc exists for the quaternion models only");
+  if (!(gamma > 0.0 && gamma < 2.0)) return fail(PGO_EINVAL, "gamma must lie in (0, 2)");
+  const size_t need = size_t(kEdgeVals) * g->n_ech + size_t(kVertVals) * g->n_vch +
+                      size_t(kRedVals) * size_t(g->G);
+  if (need > kScratchDoubles)
+    return fail(PGO_EINVAL, "the handle's reductions need " + std::to_string(need) +
+                                " doubles of the static scratch, which holds " +
+                                std::to_string(kScratchDoubles) + " (use pgo_evaluate)");
+  HIPCHK(hipSetDevice(g->device));
+  double* scr = nullptr;
+  HIPCHK(scratch_address(g->device, &scr));
+  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9, g->S9};
+  const hipError_t he =
+      g->opt.precision == PGO_FP64
+          ? launch_evaluate_noalloc<double>(view<double>(g), e, g->have_prev, g->ec_gid, g->ec_beg,
+                                            g->ec_end, g->n_ech, g->vc_gid, g->vc_beg, g->vc_end,
+                                            g->n_vch, g->g_ec_off, g->g_vc_off, g->G, scr,
+                                            beta_dev, gamma, out_dev, g->stream)
+          : launch_evaluate_noalloc<float>(view<float>(g), e, g->have_prev, g->ec_gid, g->ec_beg,
+                                           g->ec_end, g->n_ech, g->vc_gid, g->vc_beg, g->vc_end,
+                                           g->n_vch, g->g_ec_off, g->g_vc_off, g->G, scr,
+                                           beta_dev, gamma, out_dev, g->stream);
+  if (he != hipSuccess) return hip_fail(he, "evaluate_noalloc");
+  return PGO_OK;
+}
+
 pgo_status pgo_get_poses(pgo_graph* g, double* R, double* t) {
   if (!g) return fail(PGO_EINVAL, "handle is NULL");
   if (!R && !t) return PGO_OK;

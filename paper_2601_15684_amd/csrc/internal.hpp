@@ -413,6 +413,24 @@ hipError_t launch_reduce(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
                          double* partial_v, const int32_t* g_ec_off, const int32_t* g_vc_off,
                          int G, double* out, const int32_t* active, hipStream_t st);
 
+// The same reductions with partials and per-graph values in the library's
+// static device array (pgo_evaluate_noalloc): kScratchDoubles doubles per
+// device; scratch_address gives this device's array (looked up once per
+// device).  A call needs 2 n_echunks + 9 n_vchunks + 11 G doubles of it.
+// out receives kEvalVals doubles per graph: F, |p - q|, |t - s|, e,
+// beta |dq|, beta |ds|, L_beta, Psi; beta is per graph, on the device.
+constexpr size_t kScratchDoubles = size_t(1) << 18;  // 2 MiB
+constexpr int kEvalVals = 8;
+hipError_t scratch_address(int device, double** ptr);
+template <typename T>
+hipError_t launch_evaluate_noalloc(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
+                                   const int32_t* ec_graph, const int64_t* ec_beg,
+                                   const int64_t* ec_end, int n_echunks, const int32_t* vc_graph,
+                                   const int64_t* vc_beg, const int64_t* vc_end, int n_vchunks,
+                                   const int32_t* g_ec_off, const int32_t* g_vc_off, int G,
+                                   double* scr, const double* beta, double gamma, double* out,
+                                   hipStream_t st);
+
 template <typename T>
 hipError_t launch_reduce_c(const DevChordal<T>& g, const EdgeF64& e, int have_prev,
                            const int32_t* ec_graph, const int64_t* ec_beg, const int64_t* ec_end,

@@ -4,6 +4,12 @@
 // chunks that never straddle two graphs; each workgroup reduces one chunk
 // with a fixed-shape tree, then one thread per graph adds its chunks in
 // order.  No atomics, so every run gives the same bits.
+//
+// Multiply-adds are not contracted here: the device form of the residuals
+// and the merit (pgo_evaluate_noalloc) rounds as the host's.
+#pragma clang fp contract(off)
+#include <mutex>
+
 #include "internal.hpp"
 
 namespace pgo {
@@ -325,5 +331,94 @@ template hipError_t launch_reduce<double>(const DevGraph<double>&, const EdgeF64
                                           const int32_t*, const int64_t*, const int64_t*, int,
                                           double*, double*, const int32_t*, const int32_t*, int,
                                           double*, const int32_t*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// The reductions with their partial sums and per-graph values in a static
+// device array (for callers that cannot allocate; see pgo_evaluate_noalloc):
+// `scratch` lives on every device the library runs on until the process
+// ends.  Every chunk writes its own partials and every graph its own values,
+// so nothing needs clearing between calls; calls that overlap on one device
+// race on the array.
+// ---------------------------------------------------------------------------
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+
+// L_beta and the merit (as merit_of on the host, the same operations in the
+// same order) and the residuals of one graph's reduction values
+__global__ void k_eval_finish(const double* __restrict__ red, const double* __restrict__ beta,
+                              double gamma, int G, double* __restrict__ out) {
+  const int gr = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gr >= G) return;
+  const double* v = red + kRedVals * int64_t(gr);
+  const double b = beta[gr];
+  double* o = out + kEvalVals * int64_t(gr);
+  o[0] = v[kCost];
+  o[1] = sqrt(v[kPQ2]);
+  o[2] = sqrt(v[kTS2]);
+  o[3] = (v[kDL2] + v[kDZ2]) / b + b * (v[kDQ2] + v[kDT2]);
+  o[4] = b * sqrt(v[kDQ2]);
+  o[5] = b * sqrt(v[kDS2]);
+  const double a1 = fabs(1.0 - gamma) / (1.0 - fabs(1.0 - gamma));
+  const double L = v[kSplit] - v[kLamPQ] + 0.5 * b * v[kPQ2] - v[kZTS] + 0.5 * b * v[kTS2];
+  o[6] = L;
+  o[7] = L + a1 / (gamma * b) * v[kDL2];
+}
+
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[64] = {};
+
+}  // namespace
+
+hipError_t scratch_address(int device, double** ptr) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch_evaluate_noalloc(const DevGraph<T>& g, const EdgeF64& e, int have_prev,
+                                   const int32_t* ec_graph, const int64_t* ec_beg,
+                                   const int64_t* ec_end, int n_echunks, const int32_t* vc_graph,
+                                   const int64_t* vc_beg, const int64_t* vc_end, int n_vchunks,
+                                   const int32_t* g_ec_off, const int32_t* g_vc_off, int G,
+                                   double* scr, const double* beta, double gamma, double* out,
+                                   hipStream_t st) {
+  double* pe = scr;
+  double* pv = pe + size_t(kEdgeVals) * n_echunks;
+  double* red = pv + size_t(kVertVals) * n_vchunks;
+  const hipError_t err = launch_reduce<T>(g, e, have_prev, ec_graph, ec_beg, ec_end, n_echunks,
+                                          vc_graph, vc_beg, vc_end, n_vchunks, pe, pv, g_ec_off,
+                                          g_vc_off, G, red, nullptr, st);
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_eval_finish, dim3((G + 255) / 256), dim3(256), 0, st, red, beta, gamma, G,
+                     out);
+  return hipGetLastError();
+}
+
+template hipError_t launch_evaluate_noalloc<float>(const DevGraph<float>&, const EdgeF64&, int,
+                                                   const int32_t*, const int64_t*,
+                                                   const int64_t*, int, const int32_t*,
+                                                   const int64_t*, const int64_t*, int,
+                                                   const int32_t*, const int32_t*, int, double*,
+                                                   const double*, double, double*, hipStream_t);
+template hipError_t launch_evaluate_noalloc<double>(const DevGraph<double>&, const EdgeF64&, int,
+                                                    const int32_t*, const int64_t*,
+                                                    const int64_t*, int, const int32_t*,
+                                                    const int64_t*, const int64_t*, int,
+                                                    const int32_t*, const int32_t*, int, double*,
+                                                    const double*, double, double*, hipStream_t);
 
 }  // namespace pgo
