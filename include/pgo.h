@@ -384,6 +384,16 @@ pgo_status pgo_get_state_dev(pgo_graph* g, double* state_dev);
 pgo_status pgo_forward_record(pgo_graph* g, int32_t K, double beta, double gamma, int32_t C);
 
 /*
+ * pgo_record_id -- which forward pass the handle's recording is: the count
+ * of pgo_forward_record calls on the handle, or -1 when there is no
+ * recording (none made, or the edges or the state were replaced since:
+ * pgo_set_edge_params, pgo_reset_state, pgo_chordal_init).  A caller that
+ * keeps gradients of several forward passes compares it before pgo_adjoint,
+ * which always uses the latest recording.
+ */
+pgo_status pgo_record_id(pgo_graph* g, int64_t* id);
+
+/*
  * pgo_adjoint -- gradients of a scalar loss L(x^K) through the recorded
  * sweeps.  dL_dstate: device n x 21 FP64, dL/dx^K in the state layout.
  * Outputs (device FP64, caller edge order, any may be NULL): g_kappa (m),

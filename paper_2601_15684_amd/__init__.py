@@ -18,7 +18,7 @@ __all__ = [
     "pgo_set_stream", "pgo_iterate", "pgo_iterate_graphs", "pgo_cost", "pgo_merit", "pgo_evaluate", "pgo_evaluate_noalloc", "pgo_iterate_until", "pgo_solve", "pgo_residuals", "pgo_get_poses",
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
-    "pgo_get_state_dev", "pgo_forward_record", "pgo_adjoint", "pgo_chordal_init",
+    "pgo_get_state_dev", "pgo_forward_record", "pgo_record_id", "pgo_adjoint", "pgo_chordal_init",
     "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "MODEL_QUAT", "MODEL_CHORDAL",
     "MODEL_QUAT_INFO", "pgo_create_info",
     "LIB_PATH", "split_state",
@@ -81,6 +81,7 @@ _SIGNATURES = {
     "pgo_reset_state": (C.c_int, [_P]),
     "pgo_get_state_dev": (C.c_int, [_P, _P]),
     "pgo_forward_record": (C.c_int, [_P, C.c_int32, C.c_double, C.c_double, C.c_int32]),
+    "pgo_record_id": (C.c_int, [_P, C.POINTER(C.c_int64)]),
     "pgo_adjoint": (C.c_int, [_P, _P, _P, _P, _P, _P, _P]),
     "pgo_chordal_init": (C.c_int, [_P, C.c_int32, C.c_double, _I32]),
     "pgo_destroy": (None, [_P]),
@@ -324,6 +325,14 @@ def pgo_get_state_dev(h, state_dev):
 
 def pgo_forward_record(h, K, beta, gamma, C):
     _chk(lib().pgo_forward_record(h, int(K), float(beta), float(gamma), int(C)))
+
+
+def pgo_record_id(h):
+    """Count of pgo_forward_record calls on the handle, or -1 without a
+    valid recording."""
+    v = C.c_int64()
+    _chk(lib().pgo_record_id(h, C.byref(v)))
+    return int(v.value)
 
 
 def pgo_adjoint(h, dL_dstate_dev, g_kappa=0, g_tau=0, g_tm=0, g_omega=0, dL_dstate0=0):

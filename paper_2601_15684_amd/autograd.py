@@ -16,8 +16,8 @@ state is n x 21: p(4) q(4) t(3) s(3) lambda(4) z(3) after K sweeps.
 """
 import torch
 
-from . import (pgo_adjoint, pgo_forward_record, pgo_get_state_dev, pgo_info, pgo_reset_state,
-               pgo_set_edge_params, pgo_set_stream)
+from . import (pgo_adjoint, pgo_forward_record, pgo_get_state_dev, pgo_info, pgo_record_id,
+               pgo_reset_state, pgo_set_edge_params, pgo_set_stream)
 
 
 _SIDE = {}
@@ -52,11 +52,16 @@ class UnrolledPRADMM(torch.autograd.Function):
         cur.wait_stream(side)
         ctx.graph = graph
         ctx.m = info["m"]
+        ctx.record = pgo_record_id(h)
         return state
 
     @staticmethod
     def backward(ctx, grad_state):
         h = ctx.graph.h
+        if pgo_record_id(h) != ctx.record:
+            raise RuntimeError("the handle's recorded forward pass is no longer this one (a later "
+                               "forward on the same handle replaced it): run backward before the "
+                               "next forward, or use one handle per forward pass")
         dev = grad_state.device
         g = grad_state.contiguous().to(torch.float64)
         gk = torch.empty(ctx.m, dtype=torch.float64, device=dev)

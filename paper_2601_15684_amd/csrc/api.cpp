@@ -74,6 +74,7 @@ struct pgo_graph {
   int32_t *pos_out = nullptr, *pos_in = nullptr, *in2out = nullptr, *out2in = nullptr;
   std::vector<void*> sets;          // state sets: checkpoints, then segment snapshots
   int32_t rec_K = -1, rec_C = 0;
+  int64_t rec_id = 0;               // count of pgo_forward_record calls on the handle
   double rec_beta = 0, rec_gamma = 0;
   void* adj[14] = {};               // vertex adjoints (6) and edge messages (8)
   void* gacc[4] = {};               // FP64 edge-gradient accumulators
@@ -1410,6 +1411,27 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
   std::vector<double> saved(size_t(state_width(g)) * g->n);
   pgo_status s = pgo_get_state(g, saved.data());
   if (s != PGO_OK) return s;
+  // the candidates' runs overwrite the penalties, gamma and the residual
+  // history (values before the last sweep) that pgo_merit, pgo_residuals
+  // and pgo_evaluate use: keep them and put them back
+  const std::vector<double> beta_keep = g->beta_h;
+  const double gamma_keep = g->last_gamma;
+  const bool prev_keep = g->have_prev;
+  size_t vb[6];
+  state_array_bytes(g, vb);
+  void* prev[5] = {g->q_prev, g->lam_prev, g->t_prev, g->s_prev, g->z_prev};
+  const size_t prev_bytes[5] = {vb[1], vb[2], vb[3], vb[4], vb[5]};
+  void* hist[5] = {};
+  auto release = [&]() {
+    for (void* p : hist) dfree(g, p);
+  };
+  for (int k = 0; k < 5 && prev_keep; ++k) {
+    if ((s = dalloc_bytes(g, &hist[k], prev_bytes[k] * size_t(g->n))) != PGO_OK) {
+      release();
+      return s;
+    }
+    HIPCHK(launch_copy(hist[k], prev[k], prev_bytes[k] * size_t(g->n), g->stream));
+  }
   struct Cand {
     int sched, block, lds;
   };
@@ -1449,14 +1471,27 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   g->graph_lds = lds_before;
-  if (s != PGO_OK) return s;
+  if (s != PGO_OK) {
+    release();
+    return s;
+  }
   g->sched = pick.sched;
   if (pick.sched == PGO_SCHED_GRAPH) g->graph_lds = pick.lds;
   if (pick.sched == PGO_SCHED_GRAPH)
     g->block_graph = pick.block;
   else
     g->block_phase = pick.block;
-  return pgo_set_state(g, saved.data());
+  s = pgo_set_state(g, saved.data());
+  if (s == PGO_OK && prev_keep) {
+    for (int k = 0; k < 5; ++k)
+      HIPCHK(launch_copy(prev[k], hist[k], prev_bytes[k] * size_t(g->n), g->stream));
+    HIPCHK(hipStreamSynchronize(g->stream));
+  }
+  release();
+  g->beta_h = beta_keep;
+  g->last_gamma = gamma_keep;
+  g->have_prev = prev_keep;
+  return s;
 }
 
 pgo_status pgo_set_edge_params(pgo_graph* g, const double* kappa, const double* tau,
@@ -1690,6 +1725,13 @@ pgo_status pgo_forward_record(pgo_graph* g, int32_t K, double beta, double gamma
   g->rec_C = C;
   g->rec_beta = beta;
   g->rec_gamma = gamma;
+  ++g->rec_id;
+  return PGO_OK;
+}
+
+pgo_status pgo_record_id(pgo_graph* g, int64_t* id) {
+  if (!g || !id) return fail(PGO_EINVAL, "NULL argument");
+  *id = g->rec_K >= 1 ? g->rec_id : -1;
   return PGO_OK;
 }
 

@@ -195,3 +195,38 @@ def test_adjoint_requires_a_recorded_pass(pgo):
         with pytest.raises(pgo.PgoError) as ex:
             pgo.pgo_set_edge_params(h.h, bad.data_ptr(), 0, 0, 0)
         assert ex.value.name == "PGO_EINVAL" and "kappa entry 3" in str(ex.value)
+
+
+def test_backward_of_a_replaced_forward_raises(pgo):
+    """Two forward passes on one handle: the handle keeps only the latest
+    recording, so the first pass's backward raises instead of returning the
+    second pass's gradients; the second pass's backward works, and equals a
+    lone forward/backward with its parameters."""
+    from paper_2601_15684_amd.autograd import unrolled_pradmm
+    g = S.grid(4, 3, 3, all_pairs=True, sigma_R=0.05, sigma_t=0.1, seed=1)
+    beta = 0.05 * abar(g)
+    t_gt = cuda(g.t_gt)
+
+    def leaves(scale):
+        return [cuda(g.kappa * scale).requires_grad_(), cuda(g.tau).requires_grad_(),
+                cuda(g.tm).requires_grad_(), cuda(np.zeros((g.m, 3))).requires_grad_()]
+
+    with pgo.PoseGraph.from_graph(g, precision="fp64") as h:
+        a, b = leaves(1.0), leaves(2.0)
+        sa = unrolled_pradmm(h, *a, 6, beta, GAMMA, 3)
+        id_a = pgo.pgo_record_id(h.h)
+        sb = unrolled_pradmm(h, *b, 6, beta, GAMMA, 3)
+        assert pgo.pgo_record_id(h.h) == id_a + 1
+        with pytest.raises(RuntimeError, match="no longer this one"):
+            ((sa[:, 8:11] - t_gt) ** 2).sum().backward()
+        ((sb[:, 8:11] - t_gt) ** 2).sum().backward()
+        got = b[0].grad.cpu().numpy()
+        pgo.pgo_set_edge_params(h.h, b[0].data_ptr(), 0, 0, 0)
+        assert pgo.pgo_record_id(h.h) == -1        # new edges: the recording is void
+    torch.cuda.synchronize()
+    with pgo.PoseGraph.from_graph(g, precision="fp64") as h:
+        c = leaves(2.0)
+        sc = unrolled_pradmm(h, *c, 6, beta, GAMMA, 3)
+        ((sc[:, 8:11] - t_gt) ** 2).sum().backward()
+    torch.cuda.synchronize()
+    assert np.array_equal(got, c[0].grad.cpu().numpy())

@@ -199,3 +199,21 @@ def test_stopping_rule_of_the_other_models(pgo, model):
         _, done_solve, _ = h.solve(300, 20, GAMMA, betas.copy(), tol=tol, beta_growth=1.0)
         assert np.array_equal(done, done_solve) and np.array_equal(state, h.state())
     assert (done < 300).any()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_autotune_keeps_state_penalties_and_residual_history(pgo, prec):
+    """pgo_autotune times its candidates on the handle's state and puts it
+    back: the state, the per-graph penalties, gamma and the residual history
+    that pgo_evaluate (cost, residuals, merit) reads are those of before."""
+    b = S.batched(4096, first=60, count=4)
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs]) * np.array([1.0, 2.0, 3.0, 4.0])
+    with pgo.PoseGraph.from_batch(b, precision=prec) as h:
+        h.iterate(5, betas, 1.7)
+        state = h.state()
+        before = pgo.pgo_evaluate(h.h)
+        pgo.pgo_autotune(h.h, float(np.median(betas)), 1.4, 3)
+        assert np.array_equal(h.state(), state)
+        after = pgo.pgo_evaluate(h.h)
+        for x, y in zip(before, after):
+            assert np.array_equal(x, y)
