@@ -1,0 +1,149 @@
+"""Pins of the oracle's sparse damped Newton on model (1) (oracle/gn.py
+sparse_local_min), the method that writes the reference minima F* of the
+time-to-tolerance measurements:
+
+  * its analytic Jacobian against central differences of the residuals
+    under the same left increments (p <- Exp(d/2) p, t <- t + u);
+  * its Hessian 2 (J^T J + S) against second differences of the cost in
+    the same chart (and J^T J alone visibly off it);
+  * on tiny graphs, the same minimum as scipy's dense Levenberg-Marquardt
+    (a library routine on the same residuals, another parametrisation);
+  * on a noise-free graph from a perturbed start, cost 0 (ground truth is a
+    zero-cost minimum);
+  * on grid-1k from the chordal start, the stored F* that scipy's
+    trust-region least squares wrote (tests/golden/fstar_grid1k.json);
+  * the stored batch sample (tests/golden/fstar_batch_sample.json) spans the
+    three topologies and the size range, lies below each graph's chordal
+    start, and its smallest graph's F* is reproduced.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import pgo_synth as S
+from oracle import chordal_init as CI
+from oracle import gn, prep
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def problem(g, start=None):
+    if start is None:
+        P, p0, t0 = prep.prepare_graph(g)
+    else:
+        P, p0, t0 = prep.prepare(g.n, g.ei, g.ej, g.Rm, g.tm, g.kappa, g.tau, *start)
+    args = (P["ei"].numpy(), P["ej"].numpy(), P["qm"].numpy(), P["tm"].numpy(),
+            P["kappa"].numpy(), P["tau"].numpy())
+    return p0.numpy(), t0.numpy(), args
+
+
+def residual_at(p, t, args):
+    return gn.residual(np.concatenate([p.ravel(), t.ravel()]), len(p), *args)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_jacobian_matches_central_differences(seed):
+    g = S.random_small(6, 5, seed=seed, sigma_R=0.2, sigma_t=0.2)
+    p, t, args = problem(g)
+    rng = np.random.default_rng(seed)
+    p = gn._qmul(gn._qexp_half(rng.normal(0, 0.3, (g.n, 3))), p)   # away from the start
+    t = t + rng.normal(0, 0.3, t.shape)
+    J = gn._jacobian(p, t, *args).toarray()
+    h = 1e-6
+    fd = np.zeros_like(J)
+    for i in range(g.n):
+        for c in range(6):
+            d = np.zeros((g.n, 6))
+            d[i, c] = h
+            cols = []
+            for sgn in (1, -1):
+                pp = gn._qmul(gn._qexp_half(sgn * d[:, :3]), p)
+                cols.append(residual_at(pp, t + sgn * d[:, 3:], args))
+            fd[:, 6 * i + c] = (cols[0] - cols[1]) / (2 * h)
+    assert np.abs(J - fd).max() <= 1e-7 * max(1.0, np.abs(J).max())
+
+
+def test_hessian_matches_second_differences():
+    g = S.random_small(6, 5, seed=0, sigma_R=0.3, sigma_t=0.3)
+    p, t, args = problem(g)
+    rng = np.random.default_rng(0)
+    p = gn._qmul(gn._qexp_half(rng.normal(0, 0.3, (g.n, 3))), p)
+    t = t + rng.normal(0, 0.3, t.shape)
+    r = residual_at(p, t, args)
+    J = gn._jacobian(p, t, *args)
+    H = 2 * (J.T @ J + gn._second_order(p, t, r, *args)).toarray()
+    HGN = 2 * (J.T @ J).toarray()
+
+    def F(d):
+        d = d.reshape(g.n, 6)
+        rr = residual_at(gn._qmul(gn._qexp_half(d[:, :3]), p), t + d[:, 3:], args)
+        return rr @ rr
+
+    N, h = 6 * g.n, 1e-4
+    E = np.eye(N) * h
+    fd = np.zeros((N, N))
+    for a in range(N):
+        for b in range(a, N):
+            fd[a, b] = fd[b, a] = (F(E[a] + E[b]) - F(E[a] - E[b]) - F(E[b] - E[a])
+                                   + F(-E[a] - E[b])) / (4 * h * h)
+    scale = np.abs(H).max()
+    assert np.abs(H - fd).max() <= 1e-6 * scale
+    assert np.abs(HGN - fd).max() >= 1e-2 * scale     # the second-order terms matter here
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_graphs_same_minimum_as_dense_lm(seed):
+    g = S.random_small(6, 5, seed=seed, sigma_R=0.1, sigma_t=0.1)
+    p0, t0, args = problem(g)
+    c_dense, _, _ = gn.local_min(p0, t0, *args)
+    c_sparse, p, t, info = gn.sparse_local_min(p0, t0, *args)
+    assert abs(c_sparse - c_dense) <= 1e-9 * c_dense
+    assert abs(gn.model_cost(p, t, *args) - c_sparse) <= 1e-12 * c_sparse
+    assert np.allclose(np.linalg.norm(p, axis=1), 1.0, atol=1e-14)
+
+
+def test_noise_free_graph_reaches_zero_cost():
+    g = S.grid(3, 3, 2, p=0.5, sigma_R=0.0, sigma_t=0.0, seed=4)
+    _, _, args = problem(g)
+    rng = np.random.default_rng(0)
+    p_gt = prep.rot_to_quat(torch.tensor(g.R_gt)).numpy()
+    p0 = gn._qmul(gn._qexp_half(rng.normal(0, 0.05, (g.n, 3))), p_gt)
+    t0 = g.t_gt + rng.normal(0, 0.05, g.t_gt.shape)
+    F0 = gn.model_cost(p0, t0, *args)
+    F, _, _, _ = gn.sparse_local_min(p0, t0, *args)
+    assert F0 > 1e-2 and F <= 1e-18 * max(F0, 1.0) + 1e-20
+
+
+def test_grid1k_reaches_the_stored_minimum():
+    rec = json.load(open(os.path.join(GOLDEN, "fstar_grid1k.json")))
+    g = S.make_config("grid-1k")
+    Rc, tc = CI.chordal_init_graph(g)
+    p0, t0, args = problem(g, (Rc, tc))
+    F, _, _, info = gn.sparse_local_min(p0, t0, *args)
+    assert abs(F - rec["F_star"]) <= 1e-9 * rec["F_star"], (F, rec["F_star"])
+    assert info["grad_max"] <= 1e-4 * rec["F_star"]
+
+
+def test_batch_sample_spans_the_workload():
+    path = os.path.join(GOLDEN, "fstar_batch_sample.json")
+    if not os.path.exists(path):
+        pytest.skip("fstar_batch_sample.json not written")
+    rec = json.load(open(path))["graphs"]
+    assert len(rec) >= 32
+    assert {r["kind"] for r in rec} == {"circle", "grid", "sphere"}
+    n = [r["n"] for r in rec]
+    assert min(n) < 300 and max(n) > 4500
+    for r in rec:
+        assert 0 < r["F_star"] <= r["F_chordal_start"], r
+        assert r["stop"] in ("ftol", "rounding") and r["last_rel_decrease"] < 1e-10, r
+    small = min(rec, key=lambda r: r["n"])
+    g = S.batched(4096, first=small["index"], count=1).graphs[0]
+    assert g.name == small["name"]
+    Rc, tc = CI.chordal_init_graph(g)
+    p0, t0, args = problem(g, (Rc, tc))
+    assert abs(gn.model_cost(p0, t0, *args) - small["F_chordal_start"]) <= 1e-9 * small["F_chordal_start"]
+    F, _, _, _ = gn.sparse_local_min(p0, t0, *args)
+    assert abs(F - small["F_star"]) <= 1e-9 * small["F_star"]
