@@ -70,9 +70,14 @@ typedef enum {
   PGO_SCHED_AUTO = 0,  /* per graph for at least 256 graphs of at most 8192
                           poses, else per phase (or the autotuner's choice) */
   PGO_SCHED_PHASE = 1, /* one kernel launch per phase; any graph size */
-  PGO_SCHED_GRAPH = 2  /* one persistent workgroup per graph runs all the
+  PGO_SCHED_GRAPH = 2, /* one persistent workgroup per graph runs all the
                           sweeps of one pgo_iterate call (graphs of at most
                           PGO_GRAPH_SCHED_MAX_N vertices) */
+  PGO_SCHED_COOP = 3   /* one persistent cooperative launch runs all the
+                          sweeps of one pgo_iterate call, every phase over
+                          all vertices with a device-wide barrier between
+                          phases; bitwise the state of PGO_SCHED_PHASE;
+                          quaternion model (PGO_MODEL_QUAT) only */
 } pgo_schedule;
 
 #define PGO_GRAPH_SCHED_MAX_N 65536

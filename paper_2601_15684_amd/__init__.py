@@ -19,14 +19,14 @@ __all__ = [
     "pgo_get_state", "pgo_set_state", "pgo_get_prepared", "pgo_info", "pgo_autotune",
     "pgo_destroy", "pgo_last_error", "PoseGraph", "pgo_set_edge_params", "pgo_reset_state",
     "pgo_get_state_dev", "pgo_forward_record", "pgo_record_id", "pgo_adjoint", "pgo_chordal_init",
-    "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "MODEL_QUAT", "MODEL_CHORDAL",
+    "FP64", "FP32", "SCHED_AUTO", "SCHED_PHASE", "SCHED_GRAPH", "SCHED_COOP", "MODEL_QUAT", "MODEL_CHORDAL",
     "MODEL_QUAT_INFO", "pgo_create_info",
     "LIB_PATH", "split_state",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpgo.so")
 FP64, FP32 = 0, 1
-SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH = 0, 1, 2
+SCHED_AUTO, SCHED_PHASE, SCHED_GRAPH, SCHED_COOP = 0, 1, 2, 3
 MODEL_QUAT, MODEL_CHORDAL, MODEL_QUAT_INFO = 0, 1, 2
 STATE_WIDTH = {MODEL_QUAT: 21, MODEL_CHORDAL: 36, MODEL_QUAT_INFO: 21}
 STATUS = {0: "PGO_OK", 1: "PGO_EINVAL", 2: "PGO_ENOMEM", 3: "PGO_EDEVICE", 4: "PGO_ENUMERIC",
@@ -142,7 +142,8 @@ def pgo_default_options(**kw) -> PgoOptions:
         elif k == "precision" and isinstance(v, str):
             o.precision = {"fp64": FP64, "fp32": FP32}[v]
         elif k == "schedule" and isinstance(v, str):
-            o.schedule = {"auto": SCHED_AUTO, "phase": SCHED_PHASE, "graph": SCHED_GRAPH}[v]
+            o.schedule = {"auto": SCHED_AUTO, "phase": SCHED_PHASE, "graph": SCHED_GRAPH,
+                          "coop": SCHED_COOP}[v]
         elif k == "model" and isinstance(v, str):
             o.model = {"quat": MODEL_QUAT, "chordal": MODEL_CHORDAL, "info": MODEL_QUAT_INFO}[v]
         else:

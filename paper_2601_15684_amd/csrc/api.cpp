@@ -85,6 +85,7 @@ struct pgo_graph {
   void *cQ = nullptr, *cT = nullptr, *cS = nullptr;
   void *p = nullptr, *q = nullptr, *lam = nullptr, *t = nullptr, *s = nullptr, *z = nullptr;
   void *xy = nullptr, *xm = nullptr;  // sweep scratch slot (quaternion models)
+  unsigned* coop_bar = nullptr;       // barrier counter of the cooperative schedule
   void *q_prev = nullptr, *lam_prev = nullptr, *t_prev = nullptr, *s_prev = nullptr,
        *z_prev = nullptr;
   int32_t *ei = nullptr, *ej = nullptr;
@@ -100,7 +101,7 @@ struct pgo_graph {
   double *part_e = nullptr, *part_v = nullptr, *red_out = nullptr;
   double* iobuf = nullptr;  // n x state width doubles, allocated on first use
   int sched = PGO_SCHED_PHASE;
-  int block_phase = 256;
+  int block_phase = 256;  // per-phase and cooperative schedules
   int block_graph = 256;
   int graph_lds = 1;  // per-graph kernels keep each graph's state in LDS as far as it fits
   bool have_prev = false;
@@ -235,8 +236,10 @@ pgo_status check_options(const pgo_options& o) {
       return fail(PGO_EINVAL, "proximal weights h1..h4 must be finite and > 0");
   if (o.precision != PGO_FP64 && o.precision != PGO_FP32)
     return fail(PGO_EINVAL, "precision must be PGO_FP64 or PGO_FP32");
-  if (o.schedule < PGO_SCHED_AUTO || o.schedule > PGO_SCHED_GRAPH)
+  if (o.schedule < PGO_SCHED_AUTO || o.schedule > PGO_SCHED_COOP)
     return fail(PGO_EINVAL, "unknown schedule");
+  if (o.schedule == PGO_SCHED_COOP && o.model != PGO_MODEL_QUAT)
+    return fail(PGO_EINVAL, "the cooperative schedule runs the quaternion model only");
   if (o.block != 0 && (o.block < 64 || o.block > 1024 || o.block % 64 != 0))
     return fail(PGO_EINVAL, "block must be 0 or a multiple of 64 in [64, 1024]");
   if (o.model != PGO_MODEL_QUAT && o.model != PGO_MODEL_CHORDAL && o.model != PGO_MODEL_QUAT_INFO)
@@ -338,6 +341,10 @@ pgo_status alloc_precision(pgo_graph* g) {
     if ((s = dalloc_bytes(g, &g->xy, 4 * sizeof(T) * n)) != PGO_OK) return s;
     if ((s = dalloc_bytes(g, &g->xm, sizeof(T) * n)) != PGO_OK) return s;
   }
+  if (!g->chordal && !g->aniso) {
+    if ((s = dalloc(g, &g->coop_bar, 64)) != PGO_OK) return s;
+    HIPCHK(hipMemsetAsync(g->coop_bar, 0, 64 * sizeof(unsigned), g->stream));
+  }
   void** c1[] = {&g->cQ, &g->cT, &g->cS};
   for (void** v : c1)
     if ((s = dalloc_bytes(g, v, sizeof(T) * n)) != PGO_OK) return s;
@@ -423,7 +430,9 @@ pgo_status first_bad(pgo_graph* g, const uint8_t* flags_dev, int64_t count, int6
 void choose_default_schedule(pgo_graph* g) {
   const int req = g->opt.schedule;
   const bool graph_ok = g->max_n <= PGO_GRAPH_SCHED_MAX_N;
-  if (req == PGO_SCHED_GRAPH && graph_ok)
+  if (req == PGO_SCHED_COOP)
+    g->sched = PGO_SCHED_COOP;
+  else if (req == PGO_SCHED_GRAPH && graph_ok)
     g->sched = PGO_SCHED_GRAPH;
   else if (req == PGO_SCHED_PHASE || !graph_ok)
     g->sched = PGO_SCHED_PHASE;
@@ -629,6 +638,11 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
   const DevGraph<T> d = view<T>(g);
   const DevChordal<T> dc = viewc<T>(g);
   const DevAniso<T> da = viewa<T>(g);
+  if (sched == PGO_SCHED_COOP) {
+    if (g->chordal || g->aniso) return fail(PGO_EINVAL, "cooperative schedule: quaternion model only");
+    HIPCHK(launch_coop_sweeps<T>(d, k, sp, block, g->coop_bar, g->stream));
+    return PGO_OK;
+  }
   if (sched == PGO_SCHED_GRAPH) {
     if (g->chordal)
       HIPCHK(launch_graph_sweeps_c<T>(dc, g->voff32, g->order, g->G, k, sp, block, g->max_n,
@@ -1439,6 +1453,8 @@ pgo_status pgo_autotune(pgo_graph* g, double beta, double gamma, int32_t sweeps)
   const int bmax = g->aniso ? 256 : 1024, bmax_graph = g->aniso ? 512 : 1024;
   for (int b : {64, 128, 256, 512})
     if (b <= bmax) cands.push_back({PGO_SCHED_PHASE, b, 0});
+  if (!g->chordal && !g->aniso)
+    for (int b : {128, 256, 512, 1024}) cands.push_back({PGO_SCHED_COOP, b, 0});
   if (g->max_n <= PGO_GRAPH_SCHED_MAX_N)
     for (int b : {128, 256, 512, 1024}) {
       if (b > bmax_graph) continue;

@@ -207,6 +207,18 @@ hipError_t launch_graph_sweeps_stop(const DevGraph<T>& g, const int32_t* voff,
                                     const int32_t* order, int G, int k, const SweepParams& sp,
                                     int block, int max_n, int lds, hipStream_t st);
 
+// The per-phase schedule in one persistent cooperative launch (sweep_coop.hip):
+// the same phases over all vertices, a device-wide barrier on bar[0] between
+// phases (bar: 2 words of device memory owned by the handle; bar[1] is set
+// to 1 by a launch whose barrier wait timed out).  Bitwise the state of
+// launch_phase_sweeps.  coop_max_blocks: workgroups of a launch at `block`
+// threads (co-resident, at most one per compute unit).
+template <typename T>
+hipError_t launch_coop_sweeps(const DevGraph<T>& g, int k, const SweepParams& sp, int block,
+                              unsigned* bar, hipStream_t st);
+template <typename T>
+int coop_max_blocks(int block);
+
 // Boundary preparation and state transfer (prep.hip), FP64.
 // Device-to-device copy as a kernel (4-byte aligned, size a multiple of 4).
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);

@@ -95,7 +95,7 @@ def test_prepared_quaternions_match_oracle(pgo):
 
 
 @pytest.mark.parametrize("name", ["circle-100", "grid-1k", "sphere-2.5k"])
-@pytest.mark.parametrize("sched", ["phase", "graph"])
+@pytest.mark.parametrize("sched", ["phase", "graph", "coop"])
 def test_fp64_state_parity_10_sweeps(pgo, name, sched):
     g = S.make_config(name)
     beta = 0.01 * abar(g)
@@ -109,7 +109,7 @@ def test_fp64_state_parity_10_sweeps(pgo, name, sched):
 def test_fp64_edge_cases(pgo, label, g):
     beta = 0.05 * max(abar(g), 1.0)
     _, st, _ = oracle_run(g, 10, beta)
-    for sched in ("phase", "graph"):
+    for sched in ("phase", "graph", "coop"):
         for block in (64, 256):
             got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp64", schedule=sched, block=block)
             check(f"{label}/{sched}/{block}", "fp64", got, pack(st), beta)
@@ -122,7 +122,7 @@ def test_fp32_state_parity_10_sweeps(pgo, name):
     _, st, _ = oracle_run(g, 10, beta)
     ref = pack(st)
     f32 = floor(g, 10, beta, ref, "fp32")
-    for sched in ("phase", "graph"):
+    for sched in ("phase", "graph", "coop"):
         got, _, _ = gpu_run(pgo, g, 10, beta, precision="fp32", schedule=sched)
         check(f"{name}/{sched}", "fp32", got, ref, beta, f32)
 
@@ -155,7 +155,7 @@ def test_schedules_and_block_sizes_bitwise_identical(pgo):
     beta = 0.01 * abar(g)
     for prec in ("fp64", "fp32"):
         ref = None
-        for sched in ("phase", "graph"):
+        for sched in ("phase", "graph", "coop"):
             for block in (64, 256, 1024):
                 got, _, _ = gpu_run(pgo, g, 6, beta, precision=prec, schedule=sched, block=block)
                 if ref is None:
@@ -191,7 +191,7 @@ def test_batched_parity_with_oracle(pgo):
         check(gr.name, "fp64", allst[voff[k]:voff[k + 1]], ref, beta, floor(gr, 10, beta, ref, "fp64"))
 
 
-@pytest.mark.parametrize("sched", ["phase", "graph"])
+@pytest.mark.parametrize("sched", ["phase", "graph", "coop"])
 def test_per_graph_beta(pgo, sched):
     """pgo_iterate_graphs: graph g of a batch with its own beta equals the
     graph alone with that beta (bitwise) and the oracle (1e-10); the
@@ -286,7 +286,8 @@ def test_error_paths(pgo):
 
 def test_full_size_grid_100k_parity(pgo):
     """The 100k-pose grid at full size in the per-phase schedule, FP32 and
-    FP64, against the oracle after 10 sweeps."""
+    FP64, against the oracle after 10 sweeps; the cooperative schedule gives
+    the same bits at every workgroup size."""
     g = S.make_config("grid-100k")
     beta = 0.01 * abar(g)
     _, st, _ = oracle_run(g, 10, beta)
@@ -294,6 +295,9 @@ def test_full_size_grid_100k_parity(pgo):
     for prec in ("fp64", "fp32"):
         got, _, _ = gpu_run(pgo, g, 10, beta, precision=prec, schedule="phase")
         check("grid-100k/phase", prec, got, ref, beta, floor(g, 10, beta, ref, prec))
+        for block in (128, 512, 1024):
+            co, _, _ = gpu_run(pgo, g, 10, beta, precision=prec, schedule="coop", block=block)
+            assert np.array_equal(co, got), (prec, block)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -381,13 +385,39 @@ def test_degenerate_graphs_in_a_batch(pgo):
     voff, _ = b.offsets()
     for prec in ("fp64", "fp32"):
         got = {}
-        for sched, block in (("phase", 64), ("graph", 128)):
+        for sched, block in (("phase", 64), ("graph", 128), ("coop", 64)):
             with pgo.PoseGraph.from_batch(b, precision=prec, schedule=sched, block=block) as h:
                 h.iterate(10, betas, GAMMA)
                 got[sched] = h.state()
         assert np.array_equal(got["phase"], got["graph"]), prec
+        assert np.array_equal(got["phase"], got["coop"]), prec
         for k, gr in enumerate(graphs):
             _, st, _ = oracle_run(gr, 10, betas[k])
             ref = pack(st)
             check(f"degenerate batch/graph {k}", prec, got["graph"][voff[k]:voff[k + 1]], ref,
                   betas[k], floor(gr, 10, betas[k], ref, prec))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cooperative_schedule_in_the_solve_loop(pgo, prec):
+    """The cooperative schedule under pgo_solve's per-graph penalties and run
+    mask (graphs that stop or are undone skip their vertices while every
+    workgroup still meets every barrier): the same penalties, sweep counts
+    and bits as the per-phase schedule, on a batch of uneven graphs."""
+    b = S.batched(4096, first=40, count=12)
+    betas = np.array([0.002 * abar(gr) for gr in b.graphs])   # low: some chunks are undone
+    out = {}
+    for sched in ("phase", "coop"):
+        with pgo.PoseGraph.from_batch(b, precision=prec, schedule=sched) as h:
+            beta, done, conv = h.solve(200, 20, GAMMA, betas.copy(), tol=1e-3)
+            out[sched] = (beta, done, conv, h.state())
+    for a, c in zip(out["phase"], out["coop"]):
+        assert np.array_equal(a, c)
+    assert np.any(out["coop"][0] > betas) or np.any(out["coop"][1] < 200)
+
+
+def test_cooperative_schedule_refuses_other_models(pgo):
+    g = S.make_config("circle-100")
+    with pytest.raises(pgo.PgoError) as ex:
+        pgo.PoseGraph.from_graph(g, model="chordal", schedule="coop")
+    assert ex.value.name == "PGO_EINVAL"
