@@ -22,10 +22,18 @@ __device__ void polar3(const T a_in[9], T R[9], T sig[3]) {
   // convergence threshold on the largest |cos| between two columns; FP32
   // rounding alone leaves ~1e-7, so the float threshold sits above it
   constexpr T kEps = sizeof(T) == 4 ? T(3e-7) : T(1e-15);
+  // The factor does not depend on the scale of A: A is taken times 2^-e,
+  // e the binary exponent of its largest entry (exact), so that the
+  // products of squared column norms below stay finite in FP32 (entries of
+  // 1e9 and more overflow them); the singular values are scaled back.
+  T amax = T(0);
+  for (int k = 0; k < 9; ++k) amax = fmax(amax, fabs(a_in[k]));
+  int e = 0;
+  if (amax > T(0) && amax <= T(3e38)) (void)frexp(amax, &e);
   T c[3][3], v[3][3];  // c[k] = column k of A V, v[k] = column k of V
   for (int k = 0; k < 3; ++k)
     for (int r = 0; r < 3; ++r) {
-      c[k][r] = a_in[3 * r + k];
+      c[k][r] = ldexp(a_in[3 * r + k], -e);
       v[k][r] = (k == r) ? T(1) : T(0);
     }
   const int P[3] = {0, 0, 1}, Qc[3] = {1, 2, 2};
@@ -55,9 +63,10 @@ __device__ void polar3(const T a_in[9], T R[9], T sig[3]) {
     if (off < kEps) break;
   }
   for (int k = 0; k < 3; ++k) {
-    sig[k] = sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]);
-    const T inv = sig[k] > T(0) ? T(1) / sig[k] : T(0);
+    const T sk = sqrt(c[k][0] * c[k][0] + c[k][1] * c[k][1] + c[k][2] * c[k][2]);
+    const T inv = sk > T(0) ? T(1) / sk : T(0);
     for (int r = 0; r < 3; ++r) c[k][r] *= inv;
+    sig[k] = ldexp(sk, e);
   }
   for (int pass = 0; pass < 2; ++pass) {
     for (int r = 0; r < 3; ++r)

@@ -292,3 +292,23 @@ def test_solve_and_quaternion_only_calls(pgo):
             bk, dk, _ = h.solve(200, 50, GAMMA, np.array([betas[k]]), tol=0.0, beta_growth=2.0)
             assert bk[0] == beta[k] and dk[0] == done[k]
             assert np.array_equal(h.state(), allst[voff[k]:voff[k + 1]])
+
+
+def test_fp32_large_lever_arms(pgo):
+    """A 4336-pose circle of the batch (b3891: radius ~700 m, loop closures
+    spanning up to ~1.4 km) from the chordal start at the batch penalty:
+    M_i of the P update then has entries of ~1e9, whose squared column norms
+    overflow FP32 unless the polar factor scales its input.  The FP32 path
+    after 5 sweeps against the FP64 oracle, within the FP32 bounds."""
+    from oracle import chordal_init as CI
+    g = S.batched(4096, first=3891, count=1).graphs[0]
+    beta = 0.01 * abar(g)
+    Rc, tc = CI.chordal_init_graph(g)
+    g.R0, g.t0 = np.asarray(Rc), np.asarray(tc)
+    Pb, P0, t0 = C.prepare_graph(g)
+    st0 = C.init_state(P0, t0)
+    ref = T.pack_chordal(C.iterate(Pb, st0, 5, beta, GAMMA))
+    assert np.abs(ref[:, 18:21]).max() > 500.0
+    got, _, _ = gpu_run(pgo, g, 5, beta, precision="fp32", schedule="phase")
+    f32 = T.chordal_floor(Pb, st0, beta, GAMMA, 5, ref=ref)
+    check("b3891-circle-4336 (large lever arms)", "fp32", got, ref, beta, f32)
