@@ -94,9 +94,13 @@ def multistart_min(n, ei, ej, qm, tm, kappa, tau, starts=50, seed=0):
 #       blocks (d_i, d_i) = (d_j, d_j) = a I, (d_i, d_j) = -a I - [rho_v]_x / 4,
 #       (d_j, d_i) its transpose.
 # The Hessian of F = |r|^2 is 2 (J^T J + S).  Each step solves
-# (J^T J + S + mu diag(J^T J)) x = -J^T r with a sparse LU factorisation; mu
-# follows the gain-ratio rule on the quadratic model (a tenth after a step the
-# model predicts well, doubled growth after a rejected one), so near the
+# (J^T J + S + mu diag(J^T J)) x = -J^T r by a dense Cholesky factorisation
+# (LAPACK) up to 36000 unknowns -- graphs with random long-range loop
+# closures fill a sparse factorisation almost completely, and Krylov solvers
+# do not converge on these systems -- else by a sparse LU factorisation; a
+# matrix that is not positive definite counts as a rejected step.  mu
+# follows the gain-ratio rule on the quadratic model (a tenth after a step
+# the model predicts well, doubled growth after a rejected one), so near the
 # minimum the steps are Newton steps and converge quadratically.  (Gauss-
 # Newton alone, without S, stalls on these graphs: along their soft modes the
 # true curvature is a few percent of J^T J's.)  The first pose of every
@@ -184,7 +188,25 @@ def _second_order(p, t, r, ei, ej, qm, tm, kappa, tau):
                                     (6 * ej, 6 * ei, -a + np.transpose(X, (0, 2, 1)))])
 
 
-def sparse_local_min(p0, t0, ei, ej, qm, tm, kappa, tau, max_iter=200, ftol=1e-12):
+def _damped_solve(H, dg, mu, g, dense):
+    """x with (H + mu diag(dg)) x = -g, or None when the dense matrix is not
+    positive definite."""
+    import scipy.sparse as sp
+    if dense:
+        import scipy.linalg as la
+        A = H.toarray()
+        A[np.diag_indices_from(A)] += mu * dg
+        try:
+            c = la.cho_factor(A, overwrite_a=True, check_finite=False)
+        except la.LinAlgError:
+            return None
+        return la.cho_solve(c, -g, check_finite=False)
+    import scipy.sparse.linalg as spla
+    return spla.splu((H + sp.diags(mu * dg)).tocsc()).solve(-g)
+
+
+def sparse_local_min(p0, t0, ei, ej, qm, tm, kappa, tau, max_iter=200, ftol=1e-12,
+                     dense_max=36000):
     """Damped Newton on model (1) from (p0, t0) with the exact sparse Hessian
     above; returns (cost, p, t, info).  Stops once an accepted step that the
     quadratic model predicted well (gain ratio above 1/2) lowers the cost by
@@ -193,7 +215,6 @@ def sparse_local_min(p0, t0, ei, ej, qm, tm, kappa, tau, max_iter=200, ftol=1e-1
     level).  info: iterations, the final max |J^T r| over the free unknowns,
     the last accepted relative decrease, and which rule stopped the run."""
     import scipy.sparse as sp
-    import scipy.sparse.linalg as spla
     from scipy.sparse.csgraph import connected_components
     p = np.asarray(p0, float) / np.linalg.norm(p0, axis=1, keepdims=True)
     t = np.asarray(t0, float).copy()
@@ -225,7 +246,11 @@ def sparse_local_min(p0, t0, ei, ej, qm, tm, kappa, tau, max_iter=200, ftol=1e-1
         dg = np.maximum(JJ.diagonal(), 1e-12)
         nu, rho = 2.0, -1.0
         while mu <= 1e12:
-            x = spla.splu((H + sp.diags(mu * dg)).tocsc()).solve(-g)
+            x = _damped_solve(H, dg, mu, g, H.shape[0] <= dense_max)
+            if x is None:   # not positive definite: more damping
+                mu *= nu
+                nu *= 2.0
+                continue
             pred = -(2 * g @ x + x @ (H @ x))
             step = np.zeros(6 * n)
             step[free] = x

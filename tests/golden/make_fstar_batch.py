@@ -12,7 +12,7 @@ The sample: graphs sorted by pose count, cut into 32 strata of 128, one
 graph drawn from each by a seeded generator, so sizes from 50 to 5000 poses
 and the three topologies are all represented.
 
-    python tests/golden/make_fstar_batch.py [--workers 8]    # ~10 min on 8 CPUs
+    python tests/golden/make_fstar_batch.py [--workers 2 --threads 4]   # about 1.5 h on 8 CPUs
 """
 import argparse
 import json
@@ -39,11 +39,12 @@ def sample_indices():
     return sorted(int(rng.choice(s)) for s in strata)
 
 
-def solve(k):
+def solve(job):
+    k, threads = job
     import torch
     from threadpoolctl import threadpool_limits
-    torch.set_num_threads(1)
-    threadpool_limits(1)
+    torch.set_num_threads(threads)
+    threadpool_limits(threads)
     from oracle import chordal_init as CI
     from oracle import gn, prep
     g = S.batched(G, first=k, count=1).graphs[0]
@@ -64,7 +65,8 @@ def solve(k):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--workers", type=int, default=2)
+    ap.add_argument("--threads", type=int, default=4, help="BLAS threads per worker")
     args = ap.parse_args()
     idx = sample_indices()
     print(f"sampled graphs: {idx}", flush=True)
@@ -72,7 +74,8 @@ def main():
     # largest first, so the long solves do not end up last
     sizes = {k: S.batched(G, first=k, count=1).graphs[0].m for k in idx}
     with mp.get_context("fork").Pool(args.workers) as pool:
-        recs = pool.map(solve, sorted(idx, key=lambda k: -sizes[k]), chunksize=1)
+        recs = pool.map(solve, [(k, args.threads) for k in sorted(idx, key=lambda k: -sizes[k])],
+                        chunksize=1)
     recs.sort(key=lambda r: r["index"])
     out = {"workload": "batched-4096", "graphs": recs,
            "start": "oracle chordal initialisation; edge signs aligned against it",
