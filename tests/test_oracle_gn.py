@@ -147,3 +147,33 @@ def test_batch_sample_spans_the_workload():
     assert abs(gn.model_cost(p0, t0, *args) - small["F_chordal_start"]) <= 1e-9 * small["F_chordal_start"]
     F, _, _, _ = gn.sparse_local_min(p0, t0, *args)
     assert abs(F - small["F_star"]) <= 1e-9 * small["F_star"]
+
+
+def test_single_graph_minima():
+    """tests/golden/fstar_configs.json (make_fstar_configs.py): for both edge
+    sign alignments each F* lies below its start's cost (and below the
+    odometry start's), and the circle's are reproduced."""
+    path = os.path.join(GOLDEN, "fstar_configs.json")
+    if not os.path.exists(path):
+        pytest.skip("fstar_configs.json not written")
+    rec = json.load(open(path))
+    for name, r in rec.items():
+        assert r["workload"] == name
+        for sign in ("odometry", "chordal"):
+            m = r[sign]
+            assert 0 < m["F_star"] <= m["F_start"], (name, sign, m)
+            assert m["stop"] in ("ftol", "rounding") and m["last_rel_decrease"] < 1e-10, (name, m)
+        assert r["odometry"]["F_star"] < r["odometry"]["F_odometry_start"]
+    r = rec["circle-100"]
+    g = S.make_config("circle-100")
+    p0, t0, args = problem(g)
+    assert abs(gn.model_cost(p0, t0, *args) - r["odometry"]["F_odometry_start"]) <= \
+        1e-9 * r["odometry"]["F_odometry_start"]
+    Rc, tc = CI.chordal_init_graph(g)
+    pc = prep.rot_to_quat(torch.as_tensor(Rc)).numpy()
+    pc = pc * np.where((pc * p0).sum(1) < 0, -1.0, 1.0)[:, None]
+    F, _, _, _ = gn.sparse_local_min(pc, tc, *args)
+    assert abs(F - r["odometry"]["F_star"]) <= 1e-9 * r["odometry"]["F_star"]
+    pcc, tcc, argsc = problem(g, (Rc, tc))
+    F, _, _, _ = gn.sparse_local_min(pcc, tcc, *argsc)
+    assert abs(F - r["chordal"]["F_star"]) <= 1e-9 * r["chordal"]["F_star"]
