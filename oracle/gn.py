@@ -94,11 +94,12 @@ def multistart_min(n, ei, ej, qm, tm, kappa, tau, starts=50, seed=0):
 #       blocks (d_i, d_i) = (d_j, d_j) = a I, (d_i, d_j) = -a I - [rho_v]_x / 4,
 #       (d_j, d_i) its transpose.
 # The Hessian of F = |r|^2 is 2 (J^T J + S).  Each step solves
-# (J^T J + S + mu diag(J^T J)) x = -J^T r by a dense Cholesky factorisation
-# (LAPACK) up to 36000 unknowns -- graphs with random long-range loop
-# closures fill a sparse factorisation almost completely, and Krylov solvers
-# do not converge on these systems -- else by a sparse LU factorisation; a
-# matrix that is not positive definite counts as a rejected step.  mu
+# (J^T J + S + mu diag(J^T J)) x = -J^T r by a sparse LU factorisation, or
+# by a dense Cholesky factorisation (LAPACK) when the graph has long-range
+# loop closures (its reverse Cuthill-McKee bandwidth above a tenth of its
+# poses) and at most 36000 unknowns: such graphs fill a sparse factorisation
+# almost completely, and Krylov solvers do not converge on these systems.  A
+# dense matrix that is not positive definite counts as a rejected step.  mu
 # follows the gain-ratio rule on the quadratic model (a tenth after a step
 # the model predicts well, doubled growth after a rejected one), so near the
 # minimum the steps are Newton steps and converge quadratically.  (Gauss-
@@ -188,6 +189,18 @@ def _second_order(p, t, r, ei, ej, qm, tm, kappa, tau):
                                     (6 * ej, 6 * ei, -a + np.transpose(X, (0, 2, 1)))])
 
 
+def _rcm_bandwidth(n, ei, ej):
+    """Bandwidth of the pose graph's adjacency after reverse Cuthill-McKee."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import reverse_cuthill_mckee
+    A = sp.coo_matrix((np.ones(len(ei)), (ei, ej)), shape=(n, n)).tocsr()
+    A = (A + A.T).tocsr()
+    perm = reverse_cuthill_mckee(A, symmetric_mode=True)
+    pos = np.empty(n, np.int64)
+    pos[perm] = np.arange(n)
+    return int(np.abs(pos[ei] - pos[ej]).max()) if len(ei) else 0
+
+
 def _damped_solve(H, dg, mu, g, dense):
     """x with (H + mu diag(dg)) x = -g, or None when the dense matrix is not
     positive definite."""
@@ -227,6 +240,7 @@ def sparse_local_min(p0, t0, ei, ej, qm, tm, kappa, tau, max_iter=200, ftol=1e-1
     fixed = np.zeros(n, bool)
     fixed[[int(np.flatnonzero(lab == c)[0]) for c in range(lab.max() + 1)]] = True
     free = np.repeat(~fixed, 6)
+    dense = 6 * n <= dense_max and _rcm_bandwidth(n, ei, ej) > 0.1 * n
 
     def res(p_, t_):
         return residual(np.concatenate([p_.ravel(), t_.ravel()]), n, *args)
@@ -246,7 +260,7 @@ def sparse_local_min(p0, t0, ei, ej, qm, tm, kappa, tau, max_iter=200, ftol=1e-1
         dg = np.maximum(JJ.diagonal(), 1e-12)
         nu, rho = 2.0, -1.0
         while mu <= 1e12:
-            x = _damped_solve(H, dg, mu, g, H.shape[0] <= dense_max)
+            x = _damped_solve(H, dg, mu, g, dense)
             if x is None:   # not positive definite: more damping
                 mu *= nu
                 nu *= 2.0

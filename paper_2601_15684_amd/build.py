@@ -18,7 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(PKG, "libpgo.so")
-SOURCES = ["api.cpp", "prep.hip", "sweep.hip", "sweep_graph.hip", "sweep_coop.hip", "chordal.hip",
+SOURCES = ["handle.cpp", "create.cpp", "run.cpp", "evaluate.cpp", "state.cpp", "reverse.cpp",
+           "init.cpp", "prep.hip", "sweep.hip", "sweep_graph.hip", "sweep_coop.hip", "chordal.hip",
            "aniso.hip", "cinit.hip", "reduce.hip", "adjoint.hip"]
 ARCH = "gfx950"
 

@@ -1,5 +1,6 @@
-// Internal interfaces between the host side of the library (api.cpp) and the
-// kernel translation units.  Nothing here is part of the C ABI.
+// Internal interfaces between the host side of the library (handle.hpp and
+// the .cpp files) and the kernel translation units.  Nothing here is part of
+// the C ABI.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
