@@ -86,9 +86,9 @@ KERNEL_SOURCES = {  # device sources each profiled sweep kernel is built from
 
 
 def source_sha(kernel):
-    """Hash of a sweep kernel's device sources without their comments (the
-    byte counters of profiles/traffic.json hold only for the code they were
-    taken on)."""
+    """Hash of a sweep kernel's device sources without their comments and
+    white space (the byte counters of profiles/traffic.json hold only for the
+    code they were taken on)."""
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2601_15684_amd", "csrc")
@@ -96,7 +96,7 @@ def source_sha(kernel):
         code = open(os.path.join(csrc, f)).read()
         code = re.sub(r"/\*.*?\*/", "", code, flags=re.S)
         code = re.sub(r"//[^\n]*", "", code)
-        h.update(code.encode())
+        h.update(re.sub(r"\s+", "", code).encode())
     return h.hexdigest()[:16]
 
 
