@@ -77,7 +77,11 @@ typedef enum {
                           sweeps of one pgo_iterate call, every phase over
                           all vertices with a device-wide barrier between
                           phases; bitwise the state of PGO_SCHED_PHASE;
-                          quaternion model (PGO_MODEL_QUAT) only */
+                          quaternion model (PGO_MODEL_QUAT) only.  The
+                          barrier's wait is bounded (seconds): a launch
+                          whose wait runs out ends anyway and writes NaN
+                          into the first vertex's translation, so the next
+                          cost or residual call reports PGO_ENUMERIC */
 } pgo_schedule;
 
 #define PGO_GRAPH_SCHED_MAX_N 65536
