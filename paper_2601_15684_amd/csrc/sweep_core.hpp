@@ -368,6 +368,7 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const SwState<T>&
   V3<T> acc = {T(0), T(0), T(0)};
   Q4<T> y = {T(0), T(0), T(0), T(0)};
   T ymag = T(0);
+  T tau_in = T(0);  // sum_in tau: cT_i / 2, formed here instead of loaded
   struct InE {
     P4<T> u;
     Q4<T> w;
@@ -385,13 +386,14 @@ __device__ __forceinline__ void vertex_T(const DevGraph<T>& g, const SwState<T>&
         acc.x += d.u.u * d.sl.x + c.x;
         acc.y += d.u.u * d.sl.y + c.y;
         acc.z += d.u.u * d.sl.z + c.z;
+        tau_in += d.u.u;
         const Q4<T> term = qmul(d.ql, d.w);
         acc4(y, term);
         if (kF32) ymag += l1(term);
       });
   const V3<T> ti = st.t(i), si = st.s(i);
   const T b = T(sp.beta), h = T(sp.h3);
-  const T a = g.cT[i] + b + h;
+  const T a = T(2) * tau_in + b + h;
   if (save) g.t_prev[i] = ti;
   const V3<T> tn = {(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
                     (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
@@ -416,6 +418,7 @@ __device__ __forceinline__ bool vertex_S(const DevGraph<T>& g, const SwState<T>&
   constexpr bool kF32 = sizeof(T) == 4;
   const V3<T> ti = st.t(i);
   V3<T> acc = {T(0), T(0), T(0)};  // sum tau t_j
+  T tau_out = T(0);                 // sum_out tau: cS_i / 2, formed here instead of loaded
   NSum<T> ns = nsum_zero<T>();      // ns.u: sum u_e (both forms)
   struct OutE {
     P4<T> u;
@@ -427,6 +430,7 @@ __device__ __forceinline__ bool vertex_S(const DevGraph<T>& g, const SwState<T>&
         acc.x += d.u.u * d.tj.x;
         acc.y += d.u.u * d.tj.y;
         acc.z += d.u.u * d.tj.z;
+        tau_out += d.u.u;
         if (kFuse) {
           nsum_add<T, kF32>(ns, ti, d.tj, d.u);  // the next P's N (and sum u)
         } else {
@@ -440,7 +444,7 @@ __device__ __forceinline__ bool vertex_S(const DevGraph<T>& g, const SwState<T>&
   const V3<T> c = im_mul_conj(qmul_vp(qi, ns.u), pi);  // Im(q_i [0, sum u] p_i^*)
   const V3<T> zi = z;
   const T b = T(sp.beta), h = T(sp.h4);
-  const T a = g.cS[i] + b + h;
+  const T a = T(2) * tau_out + b + h;
   const V3<T> sn = {(T(2) * (acc.x - c.x) + b * ti.x - zi.x + h * si.x) / a,
                     (T(2) * (acc.y - c.y) + b * ti.y - zi.y + h * si.y) / a,
                     (T(2) * (acc.z - c.z) + b * ti.z - zi.z + h * si.z) / a};
