@@ -485,6 +485,9 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
                                          const SweepParams& sp, bool save) {
   const DevGraph<T>& g = a.g;
   V3<T> acc = {T(0), T(0), T(0)};
+  // sum_in S_e (half the system matrix's constant part), formed from the
+  // records the pass streams instead of loaded per vertex
+  V3<T> sa = {T(0), T(0), T(0)}, sb = {T(0), T(0), T(0)};
   struct InE {
     P4<T> tt;
     V3<T> sl;
@@ -502,6 +505,8 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
         const V3<T> y =
             smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.sl.x + c.x, d.sl.y + c.y, d.sl.z + c.z});
         acc.x += y.x; acc.y += y.y; acc.z += y.z;
+        sa.x += d.Sa.x; sa.y += d.Sa.y; sa.z += d.Sa.z;
+        sb.x += d.Sb.x; sb.y += d.Sb.y; sb.z += d.Sb.z;
       });
   const V3<T> ti = st.t(i), si = st.s(i);
   const V3<T> zi = st.z(i);
@@ -509,7 +514,9 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
   const V3<T> rhs = {T(2) * acc.x + b * si.x + zi.x + h * ti.x, T(2) * acc.y + b * si.y + zi.y + h * ti.y,
                      T(2) * acc.z + b * si.z + zi.z + h * ti.z};
   if (save) g.t_prev[i] = ti;
-  st.t(i) = sym_solve3(sym3<T>(a.cTa[i], a.cTb[i]), b + h, rhs);
+  st.t(i) = sym_solve3(sym3<T>(V3<T>{T(2) * sa.x, T(2) * sa.y, T(2) * sa.z},
+                               V3<T>{T(2) * sb.x, T(2) * sb.y, T(2) * sb.z}),
+                       b + h, rhs);
 }
 
 template <typename T>
@@ -520,6 +527,7 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& s
   const DevGraph<T>& g = a.g;
   const Q4<T> pi = st.p(i), qi = st.q(i);
   V3<T> acc = {T(0), T(0), T(0)};
+  V3<T> sa = {T(0), T(0), T(0)}, sb = {T(0), T(0), T(0)};  // sum_out S_e, as in T
   struct OutE {
     P4<T> tt;
     V3<T> tj;
@@ -533,13 +541,17 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& s
         const V3<T> y =
             smul(sym3<T>(d.Sa, d.Sb), V3<T>{d.tj.x - c.x, d.tj.y - c.y, d.tj.z - c.z});
         acc.x += y.x; acc.y += y.y; acc.z += y.z;
+        sa.x += d.Sa.x; sa.y += d.Sa.y; sa.z += d.Sa.z;
+        sb.x += d.Sb.x; sb.y += d.Sb.y; sb.z += d.Sb.z;
       });
   const V3<T> ti = st.t(i), si = st.s(i);
   const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h4);
   const V3<T> rhs = {T(2) * acc.x + b * ti.x - zi.x + h * si.x, T(2) * acc.y + b * ti.y - zi.y + h * si.y,
                      T(2) * acc.z + b * ti.z - zi.z + h * si.z};
-  const V3<T> sn = sym_solve3(sym3<T>(a.cSa[i], a.cSb[i]), b + h, rhs);
+  const V3<T> sn = sym_solve3(sym3<T>(V3<T>{T(2) * sa.x, T(2) * sa.y, T(2) * sa.z},
+                                      V3<T>{T(2) * sb.x, T(2) * sb.y, T(2) * sb.z}),
+                              b + h, rhs);
   const T gb = T(sp.gamma * sp.beta);
   if (save) {
     g.s_prev[i] = si;

@@ -274,6 +274,7 @@ template <typename T>
 __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, const StateC<T>& st, int i,
                                          const SweepParams& sp, bool save) {
   V3<T> acc = {T(0), T(0), T(0)};
+  T tau_in = T(0);  // sum_in tau: cT_i / 2, formed here instead of loaded
   struct InE {
     P4<T> u;
     V3<T> sl;
@@ -290,11 +291,12 @@ __device__ __forceinline__ void vertex_T(const DevChordal<T>& g, const StateC<T>
         acc.x += x.u.u * x.sl.x + c.x;
         acc.y += x.u.u * x.sl.y + c.y;
         acc.z += x.u.u * x.sl.z + c.z;
+        tau_in += x.u.u;
       });
   const V3<T> ti = st.t(i), si = st.s(i);
   const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h3);
-  const T a = g.cT[i] + b + h;
+  const T a = T(2) * tau_in + b + h;
   if (save) g.t_prev[i] = ti;
   st.t(i) = V3<T>{(T(2) * acc.x + b * si.x + zi.x + h * ti.x) / a,
                   (T(2) * acc.y + b * si.y + zi.y + h * ti.y) / a,
@@ -312,6 +314,7 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, const StateC<T>
   const V3<T> ti = st.t(i), si = st.s(i);
   const T tiv[3] = {ti.x, ti.y, ti.z};
   V3<T> acc = {T(0), T(0), T(0)};
+  T tau_out = T(0);  // sum_out tau: cS_i / 2, formed here instead of loaded
   struct OutE {
     P4<T> u;
     V3<T> tj;
@@ -323,11 +326,12 @@ __device__ __forceinline__ void vertex_S(const DevChordal<T>& g, const StateC<T>
         acc.x += x.u.u * x.tj.x - c.x;
         acc.y += x.u.u * x.tj.y - c.y;
         acc.z += x.u.u * x.tj.z - c.z;
+        tau_out += x.u.u;
         if (mo) m_out_add<T, kF32>(*mo, tiv, x.tj, x.u);  // the next P's out-edge sum
       });
   const V3<T> zi = st.z(i);
   const T b = T(sp.beta), h = T(sp.h4);
-  const T a = g.cS[i] + b + h;
+  const T a = T(2) * tau_out + b + h;
   const V3<T> sn = {(T(2) * acc.x + b * ti.x - zi.x + h * si.x) / a,
                     (T(2) * acc.y + b * ti.y - zi.y + h * si.y) / a,
                     (T(2) * acc.z + b * ti.z - zi.z + h * si.z) / a};
