@@ -323,12 +323,13 @@ __device__ __forceinline__ bool vertex_P(const DevGraph<T>& g, const SwState<T>&
   return p_finish(g, st, i, sp, qi, ti, si, pi, li, ns, y, ymag, x);
 }
 
-// Q update of vertex i; x = X_i (the tau part of the out-edge sum), lam is
+// Q update of vertex i; x = X_i (the tau part of the out-edge sum), cq =
+// cQ_i (a per-vertex constant the caller may hold in a register), lam is
 // updated in place.
 template <int U = PGO_EDGE_UNROLL, typename T>
 __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const SwState<T>& st, int i,
                                          const SweepParams& sp, bool save, Q4<T>& lam,
-                                         const Q4<T>& x, double* dsq = nullptr) {
+                                         const Q4<T>& x, T cq, double* dsq = nullptr) {
   const Q4<T> pi = st.p(i), qi = st.q(i), li = lam;
   Q4<T> acc = x;
   struct OutE {
@@ -338,7 +339,7 @@ __device__ __forceinline__ void vertex_Q(const DevGraph<T>& g, const SwState<T>&
       g.o_ptr[i], g.o_ptr[i + 1], [&](int e) { return OutE{st.p(g.o_nbr[e]), g.o_w[e]}; },
       [&](const OutE& d) { acc4(acc, qmul(d.pj, qconj(d.w))); });
   const T b = T(sp.beta), h = T(sp.h2);
-  const T a = g.cQ[i] + b + h;
+  const T a = cq + b + h;
   const Q4<T> qn = {(T(2) * acc.w + b * pi.w - li.w + h * qi.w) / a,
                     (T(2) * acc.x + b * pi.x - li.x + h * qi.x) / a,
                     (T(2) * acc.y + b * pi.y - li.y + h * qi.y) / a,
@@ -478,7 +479,7 @@ __device__ __forceinline__ void phase_mem(const DevGraph<T>& g, const SwState<T>
     g.xy[i] = x;
   } else if (PH == 1) {
     Q4<T> lam = g.lam[i];
-    vertex_Q(g, st, i, sp, save, lam, g.xy[i], dsq);
+    vertex_Q(g, st, i, sp, save, lam, g.xy[i], g.cQ[i], dsq);
     g.lam[i] = lam;
   } else if (PH == 2) {
     Q4<T> y;

@@ -7,8 +7,8 @@
 // A graph is updated by one workgroup only, so its state can stay on chip
 // for all k sweeps (loaded once, written back once):
 //   * thread t owns vertices v0 + t + r * blockDim (r < kVpt) for the whole
-//     launch and keeps their owner-only values -- lambda, z and the slot
-//     between phases -- in registers (kVpt = 0: more vertices per thread
+//     launch and keeps their owner-only values -- lambda, z, the slot
+//     between phases and the constant cQ -- in registers (kVpt = 0: more vertices per thread
 //     than registers hold; those values then stay in global memory);
 //   * the first kSlots of p, q, t, s (read by the owner and gathered by the
 //     neighbours) that fit the launch's LDS are kept there, every read of
@@ -39,6 +39,7 @@ struct Own {  // one vertex's owner-only values
   Q4<T> xy;  // Y_i from T to S+P, X_i from S+P (or the opening P) to Q
   V3<T> z;
   T xm;      // magnitude of Y_i's terms (FP32 check)
+  T cq;      // cQ_i (constant: loaded once, never stored)
 };
 
 // edges in flight per thread in the T and S passes when the owner-only
@@ -157,6 +158,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
       if (i < v1) {
         o[r].lam = g.lam[i];
         o[r].z = g.z[i];
+        o[r].cq = g.cQ[i];
         if (kXyReg) {
           o[r].xy = g.xy[i];
           o[r].xm = g.xm[i];
@@ -171,6 +173,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
       if (i < v1) {
         o[r].lam = g.lam[i];
         o[r].z = g.z[i];
+        o[r].cq = g.cQ[i];
       }
     }
   }
@@ -212,7 +215,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
 #pragma unroll
       for (int r = 0; r < kVpt; ++r) {
         const int i = vertex_of(v0 + tid + r * bd);
-        if (i < v1) vertex_Q<kUnrollQ>(g, st, i, sp, save, o[r].lam, kXyReg ? o[r].xy : g.xy[i], d);
+        if (i < v1) vertex_Q<kUnrollQ>(g, st, i, sp, save, o[r].lam, kXyReg ? o[r].xy : g.xy[i], o[r].cq, d);
       }
     } else {
       for (int i = v0 + tid; i < v1; i += bd) phase_mem<1, T>(g, st, i, sp, save, d);
