@@ -95,7 +95,16 @@ __global__ void __launch_bounds__(kRB) k_red_edges(DevGraph<T> g, EdgeF64 E,
   double v[kEdgeVals] = {0.0, 0.0};
   const int c = blockIdx.x;
   const int64_t stop = mask.skip(c) ? beg[c] : end[c];
-  for (int64_t e = beg[c] + threadIdx.x; e < stop; e += kRB) {
+  int64_t e = beg[c] + threadIdx.x;
+  for (; e + kRB < stop; e += 2 * kRB) {  // two edges' loads in flight, added in order
+    const double c0 = edge_cost(g, E, e), s0 = edge_split(g, E, e);
+    const double c1 = edge_cost(g, E, e + kRB), s1 = edge_split(g, E, e + kRB);
+    v[0] += c0;
+    v[1] += s0;
+    v[0] += c1;
+    v[1] += s1;
+  }
+  for (; e < stop; e += kRB) {
     v[0] += edge_cost(g, E, e);
     v[1] += edge_split(g, E, e);
   }
@@ -219,11 +228,27 @@ __global__ void __launch_bounds__(kRB) k_red_edges_c(DevChordal<T> g, EdgeF64 E,
   double v[kEdgeVals] = {0.0, 0.0};
   const int c = blockIdx.x;
   const int64_t stop = mask.skip(c) ? beg[c] : end[c];
-  for (int64_t e = beg[c] + threadIdx.x; e < stop; e += kRB) {
+  auto both = [&](int64_t e, double& f, double& fs) {
     const int i = E.ei[e], j = E.ej[e];
     const R3<T> Pi = g.P[i], Pj = g.P[j];
-    v[0] += edge_chordal(E, e, Pi, Pi, Pj, g.t[i], g.t[j]);
-    v[1] += edge_chordal(E, e, Pi, g.Q[i], Pj, g.s[i], g.t[j]);
+    f = edge_chordal(E, e, Pi, Pi, Pj, g.t[i], g.t[j]);
+    fs = edge_chordal(E, e, Pi, g.Q[i], Pj, g.s[i], g.t[j]);
+  };
+  int64_t e = beg[c] + threadIdx.x;
+  for (; e + kRB < stop; e += 2 * kRB) {  // two edges' loads in flight, added in order
+    double c0, s0, c1, s1;
+    both(e, c0, s0);
+    both(e + kRB, c1, s1);
+    v[0] += c0;
+    v[1] += s0;
+    v[0] += c1;
+    v[1] += s1;
+  }
+  for (; e < stop; e += kRB) {
+    double c0, s0;
+    both(e, c0, s0);
+    v[0] += c0;
+    v[1] += s0;
   }
   block_sum<kEdgeVals>(v, sh);
   if (threadIdx.x == 0)
