@@ -43,13 +43,15 @@ struct Own {  // one vertex's owner-only values
 };
 
 // edges in flight per thread in the T and S passes when the owner-only
-// values are in registers: two (measured on the 4096-graph batch, FP32: 1,
-// 2, 3, 4 give 31.9, 30.7, 31.9, 36.0 ms per 50 sweeps; three and more
-// take registers the owner-only values hold)
+// values are in registers: two in FP32 (measured on the 4096-graph batch:
+// 1, 2, 3, 4 give 31.9, 30.7, 31.9, 36.0 ms per 50 sweeps; three and more
+// take registers the owner-only values hold), one in FP64 (two: 96.6
+// against 95.0 ms)
 #ifndef PGO_UNROLL_REG
 #define PGO_UNROLL_REG 2
 #endif
-constexpr int kUnrollReg = PGO_UNROLL_REG;
+template <typename T>
+constexpr int kUnrollReg = sizeof(T) == 4 ? PGO_UNROLL_REG : 1;
 #ifndef PGO_UNROLL_Q
 #define PGO_UNROLL_Q 2
 #endif
@@ -200,7 +202,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
         const int i = vertex_of(v0 + tid + r * bd);
         if (i < v1) {
           Q4<T> x;
-          if (!vertex_P<kUnrollReg>(g, st, i, sp, o[r].lam, x)) redo |= 1u << r;
+          if (!vertex_P<kUnrollReg<T>>(g, st, i, sp, o[r].lam, x)) redo |= 1u << r;
           else if (kXyReg) o[r].xy = x;
           else g.xy[i] = x;
         }
@@ -229,7 +231,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
         if (i < v1) {
           Q4<T> y;
           T ym;
-          vertex_T<kUnrollReg>(g, st, i, sp, save, o[r].z, y, ym, d);
+          vertex_T<kUnrollReg<T>>(g, st, i, sp, save, o[r].z, y, ym, d);
           if (kXyReg) {
             o[r].xy = y;
             o[r].xm = ym;
@@ -252,7 +254,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
         if (i < v1) {
           Q4<T> xy = kXyReg ? o[r].xy : g.xy[i];
           const T ym = kXyReg ? o[r].xm : (sizeof(T) == 4 ? g.xm[i] : T(0));
-          if (!vertex_S<true, kUnrollReg>(g, st, i, sp, false, o[r].z, o[r].lam, xy, ym))
+          if (!vertex_S<true, kUnrollReg<T>>(g, st, i, sp, false, o[r].z, o[r].lam, xy, ym))
             redo |= 1u << r;
           else if (kXyReg) o[r].xy = xy;
           else g.xy[i] = xy;
@@ -269,7 +271,7 @@ __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, 
       for (int r = 0; r < kVpt; ++r) {
         const int i = vertex_of(v0 + tid + r * bd);
         Q4<T> unused = {};
-        if (i < v1) vertex_S<false, kUnrollReg>(g, st, i, sp, true, o[r].z, o[r].lam, unused, T(0), d);
+        if (i < v1) vertex_S<false, kUnrollReg<T>>(g, st, i, sp, true, o[r].z, o[r].lam, unused, T(0), d);
       }
     } else {
       for (int i = v0 + tid; i < v1; i += bd) phase_mem<3, T>(g, st, i, sp, true, d);
