@@ -32,7 +32,7 @@ process pool (which also checks sampled graphs of the batch against the GPU
 result).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 4]
-    python bench.py --steps 0 ...   # only the hipEvent-timed launches (profiling)
+    python bench.py --steps 0 ...   # only the roofline launches (profiling)
 """
 import argparse
 import hashlib
@@ -178,7 +178,8 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
     Then `plain_steps` steps of the hot path without the check (one
     persistent launch + one pass of the reductions, read back) as a second
     figure, and the persistent launch alone timed with hipEvents on the
-    handle's stream for the roofline (3 launches of `sweeps` sweeps)."""
+    handle's stream for the roofline (3 launches of `sweeps` sweeps, after
+    an untimed one)."""
     stream = torch.cuda.Stream()
     opt = P.pgo_default_options(precision=prec, schedule=sched, block=block,
                                 model=model if info is None else "quat")
@@ -235,9 +236,12 @@ def run_batch(P, torch, cat, voff, eoff, prec, betas, sweeps, steps, warmup, tun
         torch.cuda.synchronize()
         plain_wall = time.perf_counter() - t0
     # the persistent launch alone, timed with hipEvents on the handle's stream
+    # (after one untimed launch, so that the timed ones start warm also when
+    # nothing ran before them, as in a profiling run with --steps 0)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(3)]
     with torch.cuda.stream(stream):
+        P.pgo_iterate_graphs(h, sweeps, beta, GAMMA)
         for a, bb in evs:
             a.record(stream)
             P.pgo_iterate_graphs(h, sweeps, beta, GAMMA)
