@@ -325,10 +325,14 @@ def test_lds_residency_thresholds_bitwise(pgo):
     kernel (160 KiB; FP32 quaternions take 16 bytes a pose, 3-vectors 12:
     all six state arrays up to 1950 poses, five to 2275, four to 2925, three
     to 3723, two to 5120, one above; FP64 arrays are twice as wide; the
-    chordal model's arrays have their own widths) give the same bits as the
-    per-phase schedule, whose state stays in memory, for every model and
-    both precisions."""
-    sizes = [1950, 1951, 2275, 2276, 2925, 2926, 3723, 3724, 5120, 5121]
+    chordal model's arrays have their own widths) and of every register
+    variant of the quaternion kernel (owner-only values of up to 3 vertices
+    per thread with the slot between phases, up to 5 without it, at 1024
+    threads: 3072 and 5120 poses in FP32; 1 and 2 vertices in FP64: 1024 and
+    2048) give the same bits as the per-phase schedule, whose state stays in
+    memory, for every model and both precisions."""
+    sizes = [1024, 1025, 1950, 1951, 2048, 2049, 2275, 2276, 2925, 2926, 3072, 3073, 3723, 3724,
+             5120, 5121]
     graphs = [S.circle(n, n_closures=n // 2, sigma_R=0.05, sigma_t=0.05, seed=k)
               for k, n in enumerate(sizes)]
     b = S.Batch(graphs)
