@@ -672,29 +672,6 @@ __global__ void k_fill_edges_a(const int32_t* __restrict__ perm, const double* _
   Sb[k] = V3<T>{T(S[4]), T(S[5]), T(S[8])};
 }
 
-// 2 sum_in S_e and 2 sum_out S_e per vertex (FP64 sums)
-template <typename T>
-__global__ void k_vertex_consts_a(int32_t n, const int32_t* __restrict__ o_ptr,
-                                  const int32_t* __restrict__ o_perm,
-                                  const int32_t* __restrict__ i_ptr,
-                                  const int32_t* __restrict__ i_perm,
-                                  const double* __restrict__ S9, V3<T>* __restrict__ cTa,
-                                  V3<T>* __restrict__ cTb, V3<T>* __restrict__ cSa,
-                                  V3<T>* __restrict__ cSb) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  double so[6] = {0, 0, 0, 0, 0, 0}, si[6] = {0, 0, 0, 0, 0, 0};
-  const int pick[6] = {0, 1, 2, 4, 5, 8};
-  for (int k = o_ptr[i]; k < o_ptr[i + 1]; ++k)
-    for (int c = 0; c < 6; ++c) so[c] += S9[9 * int64_t(o_perm[k]) + pick[c]];
-  for (int k = i_ptr[i]; k < i_ptr[i + 1]; ++k)
-    for (int c = 0; c < 6; ++c) si[c] += S9[9 * int64_t(i_perm[k]) + pick[c]];
-  cTa[i] = V3<T>{T(2 * si[0]), T(2 * si[1]), T(2 * si[2])};
-  cTb[i] = V3<T>{T(2 * si[3]), T(2 * si[4]), T(2 * si[5])};
-  cSa[i] = V3<T>{T(2 * so[0]), T(2 * so[1]), T(2 * so[2])};
-  cSb[i] = V3<T>{T(2 * so[3]), T(2 * so[4]), T(2 * so[5])};
-}
-
 inline dim3 grid_of(int64_t count, int block) { return dim3(unsigned((count + block - 1) / block)); }
 
 }  // namespace
@@ -749,16 +726,6 @@ hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const doub
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
-                                  const int32_t* i_ptr, const int32_t* i_perm, const double* S9,
-                                  V3<T>* cTa, V3<T>* cTb, V3<T>* cSa, V3<T>* cSb, hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL((k_vertex_consts_a<T>), grid_of(n, 256), dim3(256), 0, st, n, o_ptr, o_perm,
-                     i_ptr, i_perm, S9, cTa, cTb, cSa, cSb);
-  return hipGetLastError();
-}
-
 #define PGO_ANISO_INST(T)                                                                         \
   template hipError_t launch_phase_sweeps_a<T>(const DevAniso<T>&, int, const SweepParams&, int,  \
                                                hipStream_t);                                      \
@@ -766,10 +733,7 @@ hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t
                                                const int32_t*, int, int, const SweepParams&,      \
                                                int, int, int, hipStream_t);                       \
   template hipError_t launch_fill_edges_a<T>(const int32_t*, const double*, const double*,       \
-                                             int64_t, P4<T>*, V3<T>*, V3<T>*, hipStream_t);       \
-  template hipError_t launch_vertex_consts_a<T>(int32_t, const int32_t*, const int32_t*,         \
-                                                const int32_t*, const int32_t*, const double*,   \
-                                                V3<T>*, V3<T>*, V3<T>*, V3<T>*, hipStream_t);
+                                             int64_t, P4<T>*, V3<T>*, V3<T>*, hipStream_t);
 
 PGO_ANISO_INST(float)
 PGO_ANISO_INST(double)

@@ -525,24 +525,17 @@ __global__ void k_fill_edges_c(const int32_t* __restrict__ perm, const int32_t* 
   Rw[k] = st9<T, double>(w);
 }
 
+// cQ_i = 2 sum_out kappa (FP64 sum); T and S form their sums of tau from
+// the edge records they stream
 template <typename T>
 __global__ void k_vertex_consts_c(int32_t n, const int32_t* __restrict__ o_ptr,
                                   const int32_t* __restrict__ o_perm,
-                                  const int32_t* __restrict__ i_ptr,
-                                  const int32_t* __restrict__ i_perm,
-                                  const double* __restrict__ kappa, const double* __restrict__ tau,
-                                  T* __restrict__ cQ, T* __restrict__ cT, T* __restrict__ cS) {
+                                  const double* __restrict__ kappa, T* __restrict__ cQ) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double q = 0.0, s = 0.0, t = 0.0;
-  for (int k = o_ptr[i]; k < o_ptr[i + 1]; ++k) {
-    q += kappa[o_perm[k]];
-    s += tau[o_perm[k]];
-  }
-  for (int k = i_ptr[i]; k < i_ptr[i + 1]; ++k) t += tau[i_perm[k]];
+  double q = 0.0;
+  for (int k = o_ptr[i]; k < o_ptr[i + 1]; ++k) q += kappa[o_perm[k]];
   cQ[i] = T(2.0 * q);
-  cT[i] = T(2.0 * t);
-  cS[i] = T(2.0 * s);
 }
 
 template <typename T>
@@ -677,11 +670,10 @@ hipError_t launch_fill_edges_c(const int32_t* perm, const int32_t* nbr_src, cons
 
 template <typename T>
 hipError_t launch_vertex_consts_c(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
-                                  const int32_t* i_ptr, const int32_t* i_perm, const double* kappa,
-                                  const double* tau, T* cQ, T* cT, T* cS, hipStream_t st) {
+                                  const double* kappa, T* cQ, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL((k_vertex_consts_c<T>), grid_of(n, 256), dim3(256), 0, st, n, o_ptr, o_perm,
-                     i_ptr, i_perm, kappa, tau, cQ, cT, cS);
+                     kappa, cQ);
   return hipGetLastError();
 }
 
@@ -717,8 +709,7 @@ hipError_t launch_poses_c(const DevChordal<T>& g, double* R, double* t, hipStrea
                                              const double*, const double*, const double*,       \
                                              int64_t, int32_t*, P4<T>*, R3<T>*, hipStream_t);    \
   template hipError_t launch_vertex_consts_c<T>(int32_t, const int32_t*, const int32_t*,        \
-                                                const int32_t*, const int32_t*, const double*,  \
-                                                const double*, T*, T*, T*, hipStream_t);         \
+                                                const double*, T*, hipStream_t);                 \
   template hipError_t launch_init_state_c<T>(const DevChordal<T>&, const double*, const double*, \
                                              hipStream_t);                                       \
   template hipError_t launch_state_io_c<T>(const DevChordal<T>&, double*, int, hipStream_t);    \

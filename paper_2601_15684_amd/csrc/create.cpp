@@ -124,16 +124,16 @@ pgo_status alloc_precision(pgo_graph* g) {
     if ((s = dalloc(g, &g->coop_bar, 64)) != PGO_OK) return s;
     HIPCHK(hipMemsetAsync(g->coop_bar, 0, 64 * sizeof(unsigned), g->stream));
   }
+  // cQ for every model; cT, cS for the quaternion model's reverse sweeps
   void** c1[] = {&g->cQ, &g->cT, &g->cS};
-  for (void** v : c1)
+  for (void** v : c1) {
+    if (g->chordal && v != &g->cQ) continue;
     if ((s = dalloc_bytes(g, v, sizeof(T) * n)) != PGO_OK) return s;
+  }
   if (g->aniso) {
     void** es[] = {&g->o_Sa, &g->o_Sb, &g->i_Sa, &g->i_Sb};
     for (void** v : es)
       if ((s = dalloc_bytes(g, v, 3 * sizeof(T) * m)) != PGO_OK) return s;
-    void** vs[] = {&g->cTa, &g->cTb, &g->cSa, &g->cSb};
-    for (void** v : vs)
-      if ((s = dalloc_bytes(g, v, 3 * sizeof(T) * n)) != PGO_OK) return s;
   }
   return PGO_OK;
 }
@@ -146,9 +146,8 @@ pgo_status prepare_precision(pgo_graph* g, const double* t0_dev) {
                                   static_cast<P4<T>*>(g->o_tt), static_cast<R3<T>*>(g->o_w), st));
     HIPCHK(launch_fill_edges_c<T>(g->i_perm, g->ei, g->R9, g->tm, g->kappa, g->tau, g->m, g->i_nbr,
                                   static_cast<P4<T>*>(g->i_tt), static_cast<R3<T>*>(g->i_w), st));
-    HIPCHK(launch_vertex_consts_c<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm,
-                                     g->kappa, g->tau, static_cast<T*>(g->cQ),
-                                     static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
+    HIPCHK(launch_vertex_consts_c<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->kappa,
+                                     static_cast<T*>(g->cQ), st));
     HIPCHK(launch_init_state_c<T>(viewc<T>(g), g->P0, t0_dev, st));
     return PGO_OK;
   }
@@ -164,9 +163,6 @@ pgo_status prepare_precision(pgo_graph* g, const double* t0_dev) {
                                   static_cast<V3<T>*>(g->o_Sa), static_cast<V3<T>*>(g->o_Sb), st));
     HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
                                   static_cast<V3<T>*>(g->i_Sa), static_cast<V3<T>*>(g->i_Sb), st));
-    HIPCHK(launch_vertex_consts_a<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->S9,
-                                     static_cast<V3<T>*>(g->cTa), static_cast<V3<T>*>(g->cTb),
-                                     static_cast<V3<T>*>(g->cSa), static_cast<V3<T>*>(g->cSb), st));
   }
   HIPCHK(launch_init_state<T>(view<T>(g), g->p0, t0_dev, st));
   return PGO_OK;

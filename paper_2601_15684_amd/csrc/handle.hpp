@@ -24,7 +24,6 @@ struct pgo_graph {
   bool aniso = false;               // PGO_MODEL_QUAT_INFO
   double* S9 = nullptr;             // information model: S_e per edge, caller order (m x 9)
   void *o_Sa = nullptr, *o_Sb = nullptr, *i_Sa = nullptr, *i_Sb = nullptr;
-  void *cTa = nullptr, *cTb = nullptr, *cSa = nullptr, *cSb = nullptr;
   int64_t n = 0, m = 0;
   int32_t G = 0;
   int32_t max_n = 0;
@@ -172,8 +171,6 @@ DevChordal<T> viewc(const pgo_graph* g) {
   d.i_tt = static_cast<const P4<T>*>(g->i_tt);
   d.i_R = static_cast<const R3<T>*>(g->i_w);
   d.cQ = static_cast<const T*>(g->cQ);
-  d.cT = static_cast<const T*>(g->cT);
-  d.cS = static_cast<const T*>(g->cS);
   d.P = static_cast<R3<T>*>(g->p);
   d.Q = static_cast<R3<T>*>(g->q);
   d.L = static_cast<R3<T>*>(g->lam);
@@ -192,9 +189,7 @@ template <typename T>
 DevAniso<T> viewa(const pgo_graph* g) {
   return DevAniso<T>{view<T>(g),
                      static_cast<const V3<T>*>(g->o_Sa), static_cast<const V3<T>*>(g->o_Sb),
-                     static_cast<const V3<T>*>(g->i_Sa), static_cast<const V3<T>*>(g->i_Sb),
-                     static_cast<const V3<T>*>(g->cTa), static_cast<const V3<T>*>(g->cTb),
-                     static_cast<const V3<T>*>(g->cSa), static_cast<const V3<T>*>(g->cSb)};
+                     static_cast<const V3<T>*>(g->i_Sa), static_cast<const V3<T>*>(g->i_Sb)};
 }
 
 // words of T per vertex of a rotation-like block (p, q, lambda and edge w)
@@ -234,14 +229,11 @@ pgo_status refill_edges(pgo_graph* g) {
   HIPCHK(launch_vertex_consts<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->tm,
                                  g->kappa, g->tau, static_cast<T*>(g->cQ),
                                  static_cast<T*>(g->cT), static_cast<T*>(g->cS), st));
-  if (g->aniso) {  // edge records (t~, c) and the information sums
+  if (g->aniso) {  // edge records (t~, c) and the information matrices
     HIPCHK(launch_fill_edges_a<T>(g->o_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->o_tt),
                                   static_cast<V3<T>*>(g->o_Sa), static_cast<V3<T>*>(g->o_Sb), st));
     HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
                                   static_cast<V3<T>*>(g->i_Sa), static_cast<V3<T>*>(g->i_Sb), st));
-    HIPCHK(launch_vertex_consts_a<T>(int32_t(g->n), g->o_ptr, g->o_perm, g->i_ptr, g->i_perm, g->S9,
-                                     static_cast<V3<T>*>(g->cTa), static_cast<V3<T>*>(g->cTb),
-                                     static_cast<V3<T>*>(g->cSa), static_cast<V3<T>*>(g->cSb), st));
   }
   return PGO_OK;
 }

@@ -168,8 +168,6 @@ struct DevChordal {
   const P4<T>* i_tt;
   const R3<T>* i_R;
   const T* cQ;
-  const T* cT;
-  const T* cS;
   R3<T>* P;
   R3<T>* Q;
   R3<T>* L;
@@ -255,8 +253,8 @@ hipError_t launch_poses(const DevGraph<T>& g, double* R, double* t, hipStream_t 
 // Quaternion model with a full 3x3 translation information per edge
 // (aniso.hip): the isotropic view plus the edge information matrices (two
 // P4 per edge: xx xy xz yy | yz zz) in both orders, the edge record tt
-// holding (t~, c_e) instead of (tau t~, tau), and the vertex sums
-// 2 sum_in S (cT) and 2 sum_out S (cS).
+// holding (t~, c_e) instead of (tau t~, tau).  The T and S updates form
+// their matrices 2 sum_in S and 2 sum_out S from the records they stream.
 template <typename T>
 struct DevAniso {
   DevGraph<T> g;
@@ -264,10 +262,6 @@ struct DevAniso {
   const V3<T>* o_Sb;
   const V3<T>* i_Sa;
   const V3<T>* i_Sb;
-  const V3<T>* cTa;
-  const V3<T>* cTb;
-  const V3<T>* cSa;
-  const V3<T>* cSb;
 };
 template <typename T>
 hipError_t launch_phase_sweeps_a(const DevAniso<T>& a, int k, const SweepParams& sp, int block,
@@ -281,10 +275,6 @@ hipError_t launch_graph_sweeps_a(const DevAniso<T>& a, const int32_t* voff, cons
 template <typename T>
 hipError_t launch_fill_edges_a(const int32_t* perm, const double* tm, const double* S9, int64_t m,
                                P4<T>* tt, V3<T>* Sa, V3<T>* Sb, hipStream_t st);
-template <typename T>
-hipError_t launch_vertex_consts_a(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
-                                  const int32_t* i_ptr, const int32_t* i_perm, const double* S9,
-                                  V3<T>* cTa, V3<T>* cTb, V3<T>* cSa, V3<T>* cSb, hipStream_t st);
 
 // Chordal model (chordal.hip): sweeps, preparation and state transfer.
 template <typename T>
@@ -306,8 +296,7 @@ hipError_t launch_fill_edges_c(const int32_t* perm, const int32_t* nbr_src, cons
                                int32_t* nbr, P4<T>* tt, R3<T>* Rw, hipStream_t st);
 template <typename T>
 hipError_t launch_vertex_consts_c(int32_t n, const int32_t* o_ptr, const int32_t* o_perm,
-                                  const int32_t* i_ptr, const int32_t* i_perm, const double* kappa,
-                                  const double* tau, T* cQ, T* cT, T* cS, hipStream_t st);
+                                  const double* kappa, T* cQ, hipStream_t st);
 template <typename T>
 hipError_t launch_init_state_c(const DevChordal<T>& g, const double* P0, const double* t0,
                                hipStream_t st);
