@@ -379,6 +379,7 @@ pgo_status create_impl(pgo_graph** out, int32_t G, const int64_t* voff, const in
     if ((s = alloc_precision<float>(g)) != PGO_OK) return bail(s);
     if ((s = prepare_precision<float>(g, t0d)) != PGO_OK) return bail(s);
   }
+  if ((s = reduction_edges(g)) != PGO_OK) return bail(s);
   if ((s = build_chunks(g)) != PGO_OK) return bail(s);
   he = hipStreamSynchronize(g->stream);
   if (he != hipSuccess) return bail(hip_fail(he, "prepare"));

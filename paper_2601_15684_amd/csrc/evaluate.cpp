@@ -8,6 +8,17 @@ using namespace pgo::host;
 namespace pgo {
 namespace host {
 
+namespace {
+
+// the reductions read the out-ordered copy of the FP64 edges: a chunk's
+// edges then gather their tails' state in order
+EdgeF64 reduction_view(const pgo_graph* g) {
+  return EdgeF64{g->r_ei, g->r_ej,  g->r_qe, g->r_tm, g->r_kappa, g->r_tau,
+                 g->chordal ? g->r_X9 : nullptr, g->aniso ? g->r_X9 : nullptr};
+}
+
+}  // namespace
+
 // Per-graph reduction values (RedIdx order).  Unless allow_nonfinite, a
 // non-finite value anywhere is reported as PGO_ENUMERIC.
 // active (device, G flags) restricts the work to the graphs flagged 1; the
@@ -15,7 +26,7 @@ namespace host {
 pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite,
                   const int32_t* active) {
   HIPCHK(hipSetDevice(g->device));
-  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9, g->S9};
+  const EdgeF64 e = reduction_view(g);
   hipError_t he;
   if (g->chordal && g->opt.precision == PGO_FP64)
     he = launch_reduce_c<double>(viewc<double>(g), e, g->have_prev, g->ec_gid, g->ec_beg,
@@ -120,7 +131,7 @@ pgo_status pgo_evaluate_noalloc(pgo_graph* g, const double* beta_dev, double gam
   HIPCHK(hipSetDevice(g->device));
   double* scr = nullptr;
   HIPCHK(scratch_address(g->device, &scr));
-  EdgeF64 e{g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, g->R9, g->S9};
+  const EdgeF64 e = reduction_view(g);
   const hipError_t he =
       g->opt.precision == PGO_FP64
           ? launch_evaluate_noalloc<double>(view<double>(g), e, g->have_prev, g->ec_gid, g->ec_beg,

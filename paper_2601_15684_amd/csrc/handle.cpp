@@ -58,5 +58,25 @@ pgo_status first_bad(pgo_graph* g, const uint8_t* flags_dev, int64_t count, int6
   return PGO_OK;
 }
 
+pgo_status reduction_edges(pgo_graph* g) {
+  const int64_t m = g->m;
+  if (m <= 0) return PGO_OK;
+  const double* X9 = g->chordal ? g->R9 : (g->aniso ? g->S9 : nullptr);
+  if (!g->r_ei) {
+    pgo_status s;
+    if ((s = dalloc(g, &g->r_ei, size_t(m))) != PGO_OK) return s;
+    if ((s = dalloc(g, &g->r_ej, size_t(m))) != PGO_OK) return s;
+    if (g->qe && (s = dalloc(g, &g->r_qe, size_t(m))) != PGO_OK) return s;
+    if ((s = dalloc(g, &g->r_tm, size_t(3 * m))) != PGO_OK) return s;
+    if ((s = dalloc(g, &g->r_kappa, size_t(m))) != PGO_OK) return s;
+    if ((s = dalloc(g, &g->r_tau, size_t(m))) != PGO_OK) return s;
+    if (X9 && (s = dalloc(g, &g->r_X9, size_t(9 * m))) != PGO_OK) return s;
+  }
+  HIPCHK(launch_gather_edges_f64(g->o_perm, m, g->ei, g->ej, g->qe, g->tm, g->kappa, g->tau, X9,
+                                 g->r_ei, g->r_ej, g->r_qe, g->r_tm, g->r_kappa, g->r_tau,
+                                 g->r_X9, g->stream));
+  return PGO_OK;
+}
+
 }  // namespace host
 }  // namespace pgo

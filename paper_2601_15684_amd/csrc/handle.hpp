@@ -23,6 +23,12 @@ struct pgo_graph {
   bool chordal = false;             // PGO_MODEL_CHORDAL
   bool aniso = false;               // PGO_MODEL_QUAT_INFO
   double* S9 = nullptr;             // information model: S_e per edge, caller order (m x 9)
+  // The prepared FP64 edges again in out-order (by tail, caller order among
+  // equal tails) for the reductions, whose gathers of the tail's state then
+  // run through it in order; X9 is R9 (chordal) or S9 (information model).
+  int32_t *r_ei = nullptr, *r_ej = nullptr;
+  pgo::Q4<double>* r_qe = nullptr;
+  double *r_tm = nullptr, *r_kappa = nullptr, *r_tau = nullptr, *r_X9 = nullptr;
   void *o_Sa = nullptr, *o_Sb = nullptr, *i_Sa = nullptr, *i_Sb = nullptr;
   int64_t n = 0, m = 0;
   int32_t G = 0;
@@ -217,8 +223,13 @@ pgo_status reduce(pgo_graph* g, std::vector<double>& out, bool allow_nonfinite =
 bool finite_graph(const std::vector<double>& r, int32_t j);
 void merit_of(const double* v, double beta, double gamma, double* L, double* psi);
 
+// The out-ordered FP64 edges of the reductions from the caller-ordered ones
+// (allocated on the first call).
+pgo_status reduction_edges(pgo_graph* g);
+
 // The sweep kernels' edge records and per-vertex constants, again from the
-// prepared FP64 edges (after the edge parameters or signs changed).
+// prepared FP64 edges (after the edge parameters or signs changed), and the
+// reductions' copy of those edges.
 template <typename T>
 pgo_status refill_edges(pgo_graph* g) {
   hipStream_t st = g->stream;
@@ -235,7 +246,7 @@ pgo_status refill_edges(pgo_graph* g) {
     HIPCHK(launch_fill_edges_a<T>(g->i_perm, g->tm, g->S9, g->m, static_cast<P4<T>*>(g->i_tt),
                                   static_cast<V3<T>*>(g->i_Sa), static_cast<V3<T>*>(g->i_Sb), st));
   }
-  return PGO_OK;
+  return reduction_edges(g);
 }
 
 // state.cpp

@@ -233,6 +233,14 @@ hipError_t sort_by_key(const int32_t* keys, int32_t* perm, int64_t m, int32_t n,
                        void* tmp, size_t* tmp_bytes, int32_t* keys_sorted, hipStream_t st);
 hipError_t launch_ptr_from_sorted(const int32_t* keys_sorted, int64_t m, int32_t n, int32_t* ptr,
                                   hipStream_t st);
+// The FP64 edges again in the order perm gives (row k = caller edge
+// perm[k]): ei, ej, tm, kappa, tau always; q and X9 (9 doubles per edge)
+// when given (non-null), else their outputs are left alone.
+hipError_t launch_gather_edges_f64(const int32_t* perm, int64_t m, const int32_t* ei,
+                                   const int32_t* ej, const Q4<double>* q, const double* tm,
+                                   const double* kappa, const double* tau, const double* X9,
+                                   int32_t* oi, int32_t* oj, Q4<double>* oq, double* otm,
+                                   double* okappa, double* otau, double* oX9, hipStream_t st);
 template <typename T>
 hipError_t launch_fill_edges(const int32_t* perm, const int32_t* nbr_src, const Q4<double>* qe,
                              const double* tm, const double* kappa, const double* tau, int64_t m,
@@ -378,7 +386,7 @@ hipError_t launch_cinit_cg(const CinitGraph& c, const CinitVec& v, const CinitCh
 // a graph boundary; chunk c covers [cbeg[c], cend[c]) of graph cgraph[c].
 // Partial sums of a chunk are reduced in a fixed order, then each graph sums
 // its chunks in order, so results are deterministic.
-struct EdgeF64 {  // caller-order FP64 copy of the prepared edges for the cost
+struct EdgeF64 {  // FP64 prepared edges for the cost, in any order within each graph
   const int32_t* ei;
   const int32_t* ej;
   const Q4<double>* q;

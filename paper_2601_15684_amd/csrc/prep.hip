@@ -325,6 +325,42 @@ __global__ void k_copy_words(W* __restrict__ dst, const W* __restrict__ src, int
     dst[k] = src[k];
 }
 
+__global__ void k_gather_edges_f64(const int32_t* __restrict__ perm, int64_t m,
+                                   const int32_t* __restrict__ ei, const int32_t* __restrict__ ej,
+                                   const Q4<double>* __restrict__ q, const double* __restrict__ tm,
+                                   const double* __restrict__ kappa,
+                                   const double* __restrict__ tau, const double* __restrict__ X9,
+                                   int32_t* __restrict__ oi, int32_t* __restrict__ oj,
+                                   Q4<double>* __restrict__ oq, double* __restrict__ otm,
+                                   double* __restrict__ okappa, double* __restrict__ otau,
+                                   double* __restrict__ oX9) {
+  const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  const int64_t e = perm[k];
+  oi[k] = ei[e];
+  oj[k] = ej[e];
+  if (q) oq[k] = q[e];
+  for (int c = 0; c < 3; ++c) otm[3 * k + c] = tm[3 * e + c];
+  okappa[k] = kappa[e];
+  otau[k] = tau[e];
+  if (X9)
+    for (int c = 0; c < 9; ++c) oX9[9 * k + c] = X9[9 * e + c];
+}
+
+hipError_t launch_gather_edges_f64(const int32_t* perm, int64_t m, const int32_t* ei,
+                                   const int32_t* ej, const Q4<double>* q, const double* tm,
+                                   const double* kappa, const double* tau, const double* X9,
+                                   int32_t* oi, int32_t* oj, Q4<double>* oq, double* otm,
+                                   double* okappa, double* otau, double* oX9, hipStream_t st) {
+  if (m <= 0) return hipSuccess;
+  if (!perm || !ei || !ej || !tm || !kappa || !tau || !oi || !oj || !otm || !okappa || !otau ||
+      (q && !oq) || (X9 && !oX9))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gather_edges_f64, grid_for(m, 256), dim3(256), 0, st, perm, m, ei, ej, q,
+                     tm, kappa, tau, X9, oi, oj, oq, otm, okappa, otau, oX9);
+  return hipGetLastError();
+}
+
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
   if (bytes == 0) return hipSuccess;
   const uintptr_t a = reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src);
