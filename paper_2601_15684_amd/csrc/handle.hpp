@@ -207,9 +207,12 @@ bool finite_all(const double* a, size_t k);
 pgo_status first_bad(pgo_graph* g, const uint8_t* flags_dev, int64_t count, int64_t* idx);
 
 // run.cpp: k sweeps in the given schedule and block size, one penalty per
-// handle or per graph (beta_g, host array), graphs masked by active (host)
+// handle or per graph (beta_g, host array), graphs masked by active (host);
+// snap_in_launch: the per-graph kernel copies each running graph's state to
+// the snapshot arrays before its first sweep (quaternion model only)
 pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
-                        const double* beta_g = nullptr, const int32_t* active = nullptr);
+                        const double* beta_g = nullptr, const int32_t* active = nullptr,
+                        bool snap_in_launch = false);
 // the workgroup size of the handle's current schedule
 inline int current_block(const pgo_graph* g) {
   return g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;

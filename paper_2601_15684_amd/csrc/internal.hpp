@@ -148,13 +148,17 @@ struct SweepParams {
   double tol = 0.0;
   int check_every = 0;
   int32_t* done = nullptr;
+  // per-graph kernel (quaternion model): when non-null, each graph's state
+  // p, q, lambda, t, s, z is copied to these arrays (same layout) before
+  // its first sweep, so that the call can be undone per graph
+  void* snap[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 // Device view for the rotation-matrix (chordal) model: the same edge order
 // and SoA layout, with 3x3 blocks in place of quaternions.  Edge record
 //   nbr, tt = (tau t~_e, tau_e), R = kappa_e R~_e
-// and vertex constants cQ_i = 2 sum_out kappa, cT_i = 2 sum_in tau,
-// cS_i = 2 sum_out tau.
+// and the vertex constant cQ_i = 2 sum_out kappa (T and S sum their tau
+// from the records they stream).
 template <typename T>
 struct DevChordal {
   int32_t n;

@@ -11,9 +11,14 @@ namespace {
 
 template <typename T>
 pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
-                      bool per_graph, bool masked) {
+                      bool per_graph, bool masked, bool snap_in_launch) {
   SweepParams sp{beta, gamma, g->opt.h1, g->opt.h2, g->opt.h3, g->opt.h4,
                  per_graph ? g->beta_dev : nullptr, masked ? g->active_dev : nullptr};
+  if (snap_in_launch) {
+    if (sched != PGO_SCHED_GRAPH || g->chordal || g->aniso)
+      return fail(PGO_EINVAL, "snapshot in the launch: per-graph quaternion sweeps only");
+    for (int a = 0; a < 6; ++a) sp.snap[a] = g->snap[a];
+  }
   const DevGraph<T> d = view<T>(g);
   const DevChordal<T> dc = viewc<T>(g);
   const DevAniso<T> da = viewa<T>(g);
@@ -76,17 +81,26 @@ pgo_status run_sweeps(pgo_graph* g, int32_t k, double beta, double gamma, int sc
   return PGO_OK;
 }
 
+// The snapshot arrays (allocated on first use), one per state array.
+pgo_status snapshot_alloc(pgo_graph* g) {
+  size_t vb[6];
+  state_array_bytes(g, vb);
+  for (int k = 0; k < 6; ++k)
+    if (!g->snap[k]) {
+      pgo_status s = dalloc_bytes(g, &g->snap[k], vb[k] * size_t(g->n));
+      if (s != PGO_OK) return s;
+    }
+  return PGO_OK;
+}
+
 // Copies the state into the snapshot arrays: every vertex, or (active, G
 // device flags) the vertices of the flagged graphs only.
 pgo_status snapshot(pgo_graph* g, const int32_t* active) {
   size_t vb[6];
   state_array_bytes(g, vb);
   void* cur[6] = {g->p, g->q, g->lam, g->t, g->s, g->z};
-  for (int k = 0; k < 6; ++k)
-    if (!g->snap[k]) {
-      pgo_status s = dalloc_bytes(g, &g->snap[k], vb[k] * size_t(g->n));
-      if (s != PGO_OK) return s;
-    }
+  pgo_status s = snapshot_alloc(g);
+  if (s != PGO_OK) return s;
   if (active) {
     int words[6];
     for (int k = 0; k < 6; ++k) words[k] = int(vb[k] / 4);
@@ -121,7 +135,7 @@ namespace pgo {
 namespace host {
 
 pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int sched, int block,
-                        const double* beta_g, const int32_t* active) {
+                        const double* beta_g, const int32_t* active, bool snap_in_launch) {
   const bool per_graph = beta_g != nullptr;
   const bool masked = active != nullptr;
   if (per_graph)
@@ -132,8 +146,8 @@ pgo_status iterate_with(pgo_graph* g, int32_t k, double beta, double gamma, int 
                           g->stream));
   pgo_status s =
       g->opt.precision == PGO_FP64
-          ? run_sweeps<double>(g, k, beta, gamma, sched, block, per_graph, masked)
-          : run_sweeps<float>(g, k, beta, gamma, sched, block, per_graph, masked);
+          ? run_sweeps<double>(g, k, beta, gamma, sched, block, per_graph, masked, snap_in_launch)
+          : run_sweeps<float>(g, k, beta, gamma, sched, block, per_graph, masked, snap_in_launch);
   if (s == PGO_OK) {
     g->have_prev = true;
     g->last_gamma = gamma;
@@ -273,6 +287,7 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
   pgo_status s = reduce(g, r_acc);  // values at the start: the accepted reference
   if (s != PGO_OK) return s;
   const int block = g->sched == PGO_SCHED_GRAPH ? g->block_graph : g->block_phase;
+  const bool fused_snap = g->sched == PGO_SCHED_GRAPH && !g->chordal && !g->aniso;
   g->last_gamma = gamma;
   for (;;) {
     bool any = false;
@@ -284,9 +299,12 @@ pgo_status pgo_solve(pgo_graph* g, int32_t max_sweeps, int32_t check_every, doub
     // snapshots and reductions cover the running graphs only
     HIPCHK(hipMemcpyAsync(g->active_dev, active.data(), sizeof(int32_t) * G,
                           hipMemcpyHostToDevice, g->stream));
-    if (adapt && (s = snapshot(g, g->active_dev)) != PGO_OK) return s;
-    if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta, active.data())) !=
-        PGO_OK)
+    // the per-graph quaternion kernel takes the snapshot itself as it
+    // starts each running graph (the state is read there anyway)
+    if (adapt && (s = fused_snap ? snapshot_alloc(g) : snapshot(g, g->active_dev)) != PGO_OK)
+      return s;
+    if ((s = iterate_with(g, check_every, beta[0], gamma, g->sched, block, beta, active.data(),
+                          adapt && fused_snap)) != PGO_OK)
       return s;
     if ((s = reduce(g, r, true, g->active_dev)) != PGO_OK) return s;
     bool any_restore = false;

@@ -135,6 +135,16 @@ template <int kVpt, bool kXyReg, int kSlots, bool kStop, typename T>
 __device__ __forceinline__ void graph_run(const DevGraph<T>& g, int gr, int v0, int v1, int k,
                                           const SweepParams& sp, unsigned char* lds,
                                           double* red) {
+  if (sp.snap[0]) {  // the state before the call, for undoing it (same owner mapping)
+    for (int i = v0 + int(threadIdx.x); i < v1; i += int(blockDim.x)) {
+      static_cast<Q4<T>*>(sp.snap[0])[i] = g.p[i];
+      static_cast<Q4<T>*>(sp.snap[1])[i] = g.q[i];
+      static_cast<Q4<T>*>(sp.snap[2])[i] = g.lam[i];
+      static_cast<V3<T>*>(sp.snap[3])[i] = g.t[i];
+      static_cast<V3<T>*>(sp.snap[4])[i] = g.s[i];
+      static_cast<V3<T>*>(sp.snap[5])[i] = g.z[i];
+    }
+  }
   const SwState<T> st = sw_load<kSlots>(g, v0, v1, lds);
   const int tid = int(threadIdx.x), bd = int(blockDim.x);
   Own<T> o[kVpt > 0 ? kVpt : 1];
