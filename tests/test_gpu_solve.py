@@ -96,6 +96,26 @@ def test_batched_solve_matches_single_solves(pgo):
                 assert np.array_equal(h1.state(), allst[voff[k]:voff[k + 1]]), (prec, k)
 
 
+def test_solve_with_rejections_same_in_both_schedules(pgo):
+    """The merit-checked solve undoes a rejected chunk from a snapshot that
+    the per-graph kernel takes as it starts each graph, where the per-phase
+    schedule copies the state in a pass of its own: with rejections on the
+    way (graph 106 diverges at 0.01 abar), both give the same penalties,
+    sweep counts and state, bit for bit."""
+    b = S.batched(4096, first=100, count=8)
+    betas = np.array([0.01 * abar(gr) for gr in b.graphs])
+    for prec in ("fp64", "fp32"):
+        out = {}
+        for sched in ("graph", "phase"):
+            with pgo.PoseGraph.from_batch(b, precision=prec, schedule=sched) as h:
+                bb, done, conv = h.solve(300, 50, GAMMA, betas, tol=0.0, beta_growth=2.0)
+                out[sched] = (bb, done, h.state())
+        assert np.any(out["graph"][0] > betas), prec  # some chunk was rejected
+        assert np.array_equal(out["graph"][0], out["phase"][0]), prec
+        assert np.array_equal(out["graph"][1], out["phase"][1]), prec
+        assert np.array_equal(out["graph"][2], out["phase"][2]), prec
+
+
 def test_solve_argument_checks(pgo):
     g = S.make_config("circle-100")
     with pgo.PoseGraph.from_graph(g) as h:
