@@ -2,8 +2,11 @@
 bench.py times: one handle over all 4096 graphs, per-graph schedule with
 1024-thread workgroups and the multipliers in LDS (FP32; FP64 as well), one
 beta per graph (0.01 x the graph's mean diagonal weight), 10 sweeps.
-Sampled graphs (the largest, the smallest, and six seeded picks) are run
-one by one through the FP64 oracle and compared block by block, with the
+The rotation-matrix rendering and the information model (random
+information matrices, seed 0) run the same way in their bench legs'
+configuration (FP32, 1024 and 512 threads).  Sampled graphs (the largest,
+the smallest, and six seeded picks) are run one by one through the FP64
+oracle of each model and compared block by block, with the
 bounds of the parity tests (tests/tolerance.py: raw max-abs per block,
 multipliers over beta; FP64 1e-10, FP32 max(1e-4, 4 x the float32 oracle's
 own departure on that graph)); the raw errors of every sampled graph are in
@@ -89,6 +92,62 @@ def main():
                         "worst_raw": worst, "raw_per_graph": per_graph,
                         "floor_per_graph": {batch.graphs[k].name: {c: float(f"{v:.3e}") for c, v in floors[prec][k].items()} for k in pick}}
         print(f"{prec} done", flush=True)
+
+    # the rotation-matrix rendering and the information model in the launch
+    # configuration of their bench legs (FP32, per graph, LDS residency;
+    # 1024 and 512 threads), the same sampled graphs against their oracles
+    from oracle import aniso as A
+    from oracle import chordal as C
+    infos = S.random_info(int(eoff[-1]), cat["tau"], 10.0, seed=0)
+    legs = {
+        "chordal_fp32": dict(model="chordal", block=1024, blocks=T.CHORDAL_BLOCKS),
+        "info_fp32": dict(model="info", block=512, blocks=T.QUAT_BLOCKS),
+    }
+    for leg, cfg in legs.items():
+        refs_m, floors_m = {}, {}
+        for k in pick:
+            g = batch.graphs[k]
+            if cfg["model"] == "chordal":
+                Pb, P0, t0c = C.prepare_graph(g)
+                st0 = C.init_state(P0, t0c)
+                refs_m[k] = T.pack_chordal(C.iterate(Pb, st0, SWEEPS, betas[k], GAMMA))
+                floors_m[k] = T.chordal_floor(Pb, st0, betas[k], GAMMA, SWEEPS, ref=refs_m[k])
+            else:
+                info_k = infos[eoff[k]:eoff[k + 1]]
+                Pa, pa0, ta0 = A.prepare(g.n, g.ei, g.ej, g.Rm, g.tm, g.kappa, info_k, g.R0, g.t0)
+                st0 = O.init_state(pa0, ta0)
+                refs_m[k] = T.pack_quat(A.iterate(Pa, st0, SWEEPS, betas[k], GAMMA))
+                floors_m[k] = T.info_floor(Pa, st0, betas[k], GAMMA, SWEEPS, ref=refs_m[k])
+        if cfg["model"] == "chordal":
+            opt = P.pgo_default_options(precision="fp32", schedule="graph", block=cfg["block"],
+                                        model="chordal")
+            h = P.pgo_create_batched(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"],
+                                     cat["ej"], cat["Rm"].reshape(-1, 9), cat["tm"],
+                                     cat["kappa"], cat["tau"], opt)
+        else:
+            opt = P.pgo_default_options(precision="fp32", schedule="graph", block=cfg["block"])
+            h = P.pgo_create_info(voff, eoff, cat["R0"].reshape(-1, 9), cat["t0"], cat["ei"],
+                                  cat["ej"], cat["Rm"].reshape(-1, 9), cat["tm"], cat["kappa"],
+                                  infos, opt)
+        try:
+            info = P.pgo_info(h)
+            P.pgo_iterate_graphs(h, SWEEPS, betas, GAMMA)
+            state = P.pgo_get_state(h)
+        finally:
+            P.pgo_destroy(h)
+        worst, per_graph = {}, {}
+        for k in pick:
+            e = T.block_errors(state[voff[k]:voff[k + 1]], refs_m[k], betas[k], cfg["blocks"])
+            bad = T.check(f"{cfg['model']} {batch.graphs[k].name}", "fp32", e, floors_m[k])
+            per_graph[batch.graphs[k].name] = {c: float(f"{v:.3e}") for c, v in e.items()}
+            for c, v in e.items():
+                worst[c] = max(worst.get(c, 0.0), v)
+            if bad:
+                ok = False
+                print(f"{leg}: graph {k} ({batch.graphs[k].name}) over its bound: {bad}", flush=True)
+        report[leg] = {"lds": info["lds"], "schedule": info["schedule"], "block": info["block"],
+                       "worst_raw": worst, "raw_per_graph": per_graph}
+        print(f"{leg} done", flush=True)
     print(json.dumps({"graphs": pick, "ok": ok, **report}), flush=True)
     return 0 if ok else 1
 
