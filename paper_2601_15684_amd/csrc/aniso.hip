@@ -28,6 +28,12 @@ namespace pgo {
 
 namespace {
 
+// edges in flight per thread in every edge loop: one in FP32 (the batch's
+// per-graph launch: 103.5 ms with two, 101.7 with one, 108.6 with three),
+// two in FP64
+template <typename T>
+constexpr int kUA = sizeof(T) == 4 ? 1 : 2;
+
 template <typename A>
 struct Sym3 {
   A xx, xy, xz, yy, yz, zz;
@@ -386,7 +392,7 @@ __device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
     V3<T> tj;
     V3<T> Sa, Sb;
   };
-  edge_loop(
+  edge_loop<kUA<T>>(
       g.o_ptr[i], g.o_ptr[i + 1],
       [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e]), a.o_Sa[e], a.o_Sb[e]}; },
       [&](const OutE& d) {
@@ -401,7 +407,7 @@ __device__ void vertex_P_own(const DevAniso<T>& a, const State<T>& st, int i,
   struct InE {
     Q4<T> ql, w;
   };
-  edge_loop(
+  edge_loop<kUA<T>>(
       g.i_ptr[i], g.i_ptr[i + 1], [&](int e) { return InE{st.q(g.i_nbr[e]), g.i_w[e]}; },
       [&](const InE& d) {
         const Q4<A> ql = cvt<A>(d.ql);
@@ -442,7 +448,7 @@ __device__ __forceinline__ void vertex_Q(const DevAniso<T>& a, const State<T>& s
     V3<T> Sa, Sb;
     Q4<T> pj, w;
   };
-  edge_loop(
+  edge_loop<kUA<T>>(
       g.o_ptr[i], g.o_ptr[i + 1],
       [&](int e) {
         const int j = g.o_nbr[e];
@@ -494,7 +500,7 @@ __device__ __forceinline__ void vertex_T(const DevAniso<T>& a, const State<T>& s
     V3<T> Sa, Sb;
     Q4<T> ql, pl;
   };
-  edge_loop(
+  edge_loop<kUA<T>>(
       g.i_ptr[i], g.i_ptr[i + 1],
       [&](int e) {
         const int l = g.i_nbr[e];
@@ -533,7 +539,7 @@ __device__ __forceinline__ void vertex_S(const DevAniso<T>& a, const State<T>& s
     V3<T> tj;
     V3<T> Sa, Sb;
   };
-  edge_loop(
+  edge_loop<kUA<T>>(
       g.o_ptr[i], g.o_ptr[i + 1],
       [&](int e) { return OutE{g.o_tt[e], st.t(g.o_nbr[e]), a.o_Sa[e], a.o_Sb[e]}; },
       [&](const OutE& d) {
